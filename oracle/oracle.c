@@ -1,0 +1,199 @@
+/*
+ * CPU oracle for the triangular solve L X = B.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this library.  The GPU library never links, includes or calls it, and
+ * it shares no code, header or constant with the GPU path.
+ *
+ * Problem statement (Sec. I, Introduction): L is an n x n lower-triangular
+ * matrix, B and X are dense n x k matrices, and X solves L X = B.  The
+ * inversion-based method of Sec. VI (Alg. It-Inv-TRSM) ensures B = L X, i.e.
+ * it reaches X = L^{-1} B exactly up to rounding order, so the oracle is that
+ * plain definition written out: forward substitution,
+ *
+ *     x[i][c] = ( b[i][c] - sum_{j<i} l[i][j] * x[j][c] ) / l[i][i],
+ *
+ * with i ascending, the sum taken with j ascending, IEEE binary64 arithmetic,
+ * a true division, and no contraction into fused multiply-adds (the build
+ * uses -ffp-contract=off -fno-fast-math).
+ *
+ * Threads split the right-hand-side columns: the column split of
+ * Sec. II-C.4 (L [X1 X2] = [B1 B2] gives two independent solves).  Every column
+ * is computed by exactly the same sequence of operations whatever the thread
+ * count, so the result is bitwise identical to a serial run.
+ *
+ * Storage is row-major with leading dimensions: element (i,j) of L is
+ * L[i*ldl + j], of B is B[i*ldb + c], of X is X[i*ldx + c].  Entries of L above
+ * the diagonal are never read.
+ *
+ * Only the lower triangle including the diagonal is read; a zero diagonal
+ * entry simply produces IEEE infinities / NaNs (no pivoting, no scaling).
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Column-chunk width a thread works on at a time.  Any width gives the same
+ * bits: each column's arithmetic does not depend on its neighbours. */
+#define ORACLE_COLS 64
+
+static int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+/* Forward substitution on columns [c0, c1).  Row i of X is used as the running
+ * value of every column's sum: it starts at b[i][c], then for j = 0..i-1 in
+ * order subtracts the rounded product l[i][j]*x[j][c], then is divided by
+ * l[i][i]. */
+static void subst_cols_f64(int64_t n, int64_t c0, int64_t c1,
+                           const double* L, int64_t ldl,
+                           const double* B, int64_t ldb,
+                           double* X, int64_t ldx) {
+  for (int64_t i = 0; i < n; ++i) {
+    double* xi = X + i * ldx;
+    const double* bi = B + i * ldb;
+    const double* li = L + i * ldl;
+    if (xi != bi)
+      for (int64_t c = c0; c < c1; ++c) xi[c] = bi[c];
+    for (int64_t j = 0; j < i; ++j) {
+      const double lij = li[j];
+      const double* xj = X + j * ldx;
+      for (int64_t c = c0; c < c1; ++c) {
+        double prod = lij * xj[c];
+        xi[c] = xi[c] - prod;
+      }
+    }
+    const double d = li[i];
+    for (int64_t c = c0; c < c1; ++c) xi[c] = xi[c] / d;
+  }
+}
+
+/* X = L^{-1} B by forward substitution (Sec. I problem statement).  X may be
+ * the same buffer as B (with ldx == ldb).  Returns 0, or -1 on bad sizes. */
+int oracle_trsm_f64(int64_t n, int64_t k,
+                    const double* L, int64_t ldl,
+                    const double* B, int64_t ldb,
+                    double* X, int64_t ldx, int nthreads) {
+  if (n < 0 || k < 0) return -1;
+  if (n == 0 || k == 0) return 0;
+  if (ldl < n || ldb < k || ldx < k) return -1;
+  const int64_t nchunks = (k + ORACLE_COLS - 1) / ORACLE_COLS;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int64_t c0 = ch * ORACLE_COLS;
+    const int64_t c1 = min64(k, c0 + ORACLE_COLS);
+    subst_cols_f64(n, c0, c1, L, ldl, B, ldb, X, ldx);
+  }
+  (void)nthreads;
+  return 0;
+}
+
+/* Residual R = B - L X, summed plainly: r[i][c] = b[i][c] - sum_{j<=i}
+ * l[i][j] x[j][c], j ascending, each product rounded then subtracted.
+ * This is the postcondition B = L X of Alg. It-Inv-TRSM written as a defect. */
+int oracle_residual_f64(int64_t n, int64_t k,
+                        const double* L, int64_t ldl,
+                        const double* X, int64_t ldx,
+                        const double* B, int64_t ldb,
+                        double* R, int64_t ldr, int nthreads) {
+  if (n < 0 || k < 0) return -1;
+  if (n == 0 || k == 0) return 0;
+  if (ldl < n || ldb < k || ldx < k || ldr < k) return -1;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    double* ri = R + i * ldr;
+    const double* bi = B + i * ldb;
+    const double* li = L + i * ldl;
+    for (int64_t c = 0; c < k; ++c) ri[c] = bi[c];
+    for (int64_t j = 0; j <= i; ++j) {
+      const double lij = li[j];
+      const double* xj = X + j * ldx;
+      for (int64_t c = 0; c < k; ++c) {
+        double prod = lij * xj[c];
+        ri[c] = ri[c] - prod;
+      }
+    }
+  }
+  (void)nthreads;
+  return 0;
+}
+
+/* The same forward substitution carried out in binary128 (__float128), with
+ * inputs taken exactly from binary64 and the result rounded once to binary64.
+ * Used to arbitrate accuracy questions on ill-conditioned inputs: its own
+ * error is about cond(L) * 2^-113, far below any binary64 solve. */
+int oracle_trsm_q(int64_t n, int64_t k,
+                  const double* L, int64_t ldl,
+                  const double* B, int64_t ldb,
+                  double* X, int64_t ldx, int nthreads) {
+  if (n < 0 || k < 0) return -1;
+  if (n == 0 || k == 0) return 0;
+  if (ldl < n || ldb < k || ldx < k) return -1;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int64_t c = 0; c < k; ++c) {
+    __float128* x = (__float128*)malloc(sizeof(__float128) * (size_t)n);
+    if (!x) continue;
+    for (int64_t i = 0; i < n; ++i) {
+      const double* li = L + i * ldl;
+      __float128 s = (__float128)B[i * ldb + c];
+      for (int64_t j = 0; j < i; ++j) s -= (__float128)li[j] * x[j];
+      x[i] = s / (__float128)li[i];
+    }
+    for (int64_t i = 0; i < n; ++i) X[i * ldx + c] = (double)x[i];
+    free(x);
+  }
+  (void)nthreads;
+  return 0;
+}
+
+/* Frobenius norm of the lower triangle (diagonal included) of L, and of a
+ * dense n x k matrix, accumulated in binary128 so that the norm itself is
+ * correctly rounded to binary64 for all practical sizes. */
+double oracle_fro_lower(int64_t n, const double* L, int64_t ldl) {
+  __float128 s = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      __float128 v = (__float128)L[i * ldl + j];
+      s += v * v;
+    }
+  /* square root by Newton steps in binary128, seeded from binary64 */
+  double s64 = (double)s;
+  if (s64 <= 0) return 0.0;
+  __float128 r = (__float128)__builtin_sqrt(s64);
+  for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);
+  return (double)r;
+}
+
+double oracle_fro_dense(int64_t n, int64_t k, const double* A, int64_t lda) {
+  __float128 s = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t c = 0; c < k; ++c) {
+      __float128 v = (__float128)A[i * lda + c];
+      s += v * v;
+    }
+  double s64 = (double)s;
+  if (s64 <= 0) return 0.0;
+  __float128 r = (__float128)__builtin_sqrt(s64);
+  for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);
+  return (double)r;
+}
+
+/* Number of threads the OpenMP runtime would use by default. */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

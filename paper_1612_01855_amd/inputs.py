@@ -1,0 +1,174 @@
+"""Seeded synthetic inputs for L X = B.
+
+This module holds no arithmetic of the solver: it only draws matrices.  Both
+the GPU tests/benchmark and the CPU oracle read the very same arrays produced
+here.  Every generator takes an explicit seed and uses numpy's PCG64, drawing
+in a fixed order so that one seed fixes every byte.
+
+Workload families (the paper itself runs no experiments; these stand in for
+its problem statement, an n x n lower-triangular L and a dense n x k B):
+
+* ``easy_lower``  -- diagonal ~ U[1,2], strict lower ~ U[-1,1]/n.  Strictly
+  row-diagonally dominant, so cond(L) is small (a handful).
+* ``chol_lower``  -- L = chol(G G^T / m + I), G ~ N(0,1) of size n x m,
+  m = 2n by default.  A well conditioned Cholesky factor.
+* ``hard_lower``  -- L = chol(G G^T / m + eps I) with G of size n x n/2 (so
+  G G^T has rank n/2) and eps = 1e-12 * ||G G^T / m||_2: cond_2(A) ~ 1e12,
+  hence cond_2(L) ~ 1e6.
+* ``rhs``         -- B ~ N(0,1).
+* closed-form matrices used as pins (identity, diagonal, bidiagonal,
+  all-ones lower triangle, random integer unit-lower).
+* ``serving_factors`` / ``request_stream`` -- the serving mix: factor sizes
+  log-uniform in [64, 4096], request widths log-uniform in [1, 512], Poisson
+  arrivals.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _fill_upper(L: np.ndarray, upper: Optional[float]) -> np.ndarray:
+    """Write ``upper`` strictly above the diagonal (NaN proves it is unread)."""
+    if upper is not None:
+        iu = np.triu_indices(L.shape[0], 1)
+        L[iu] = upper
+    return L
+
+
+def easy_lower(n: int, seed: int, upper: Optional[float] = 0.0) -> np.ndarray:
+    """Diagonal ~ U[1,2], strict lower ~ U[-1,1]/n (float64, row-major)."""
+    g = rng(seed)
+    d = g.uniform(1.0, 2.0, size=n)
+    L = g.uniform(-1.0, 1.0, size=(n, n))
+    L *= 1.0 / max(n, 1)
+    L = np.tril(L, -1)
+    L[np.arange(n), np.arange(n)] = d
+    return _fill_upper(L, upper)
+
+
+def rhs(n: int, k: int, seed: int) -> np.ndarray:
+    """B ~ N(0,1), n x k float64."""
+    return rng(seed + 0x5EED).standard_normal(size=(n, k))
+
+
+def easy_system(n: int, k: int, seed: int, upper: Optional[float] = 0.0):
+    return easy_lower(n, seed, upper), rhs(n, k, seed)
+
+
+def chol_lower(n: int, seed: int, m: Optional[int] = None,
+               upper: Optional[float] = 0.0) -> np.ndarray:
+    """L = chol(G G^T / m + I), G ~ N(0,1) n x m (m = 2n by default)."""
+    m = 2 * n if m is None else m
+    g = rng(seed)
+    G = g.standard_normal(size=(n, m))
+    A = G @ G.T
+    A *= 1.0 / m
+    A[np.arange(n), np.arange(n)] += 1.0
+    del G
+    L = np.linalg.cholesky(A)
+    return _fill_upper(np.ascontiguousarray(L), upper)
+
+
+def hard_lower(n: int, seed: int, upper: Optional[float] = 0.0,
+               ratio: float = 1e-12) -> np.ndarray:
+    """L = chol(G G^T / m + eps I), G ~ N(0,1) n x m, m = max(n//2, 1),
+    eps = ratio * lambda_max(G G^T / m) (lambda_max by 50 seeded power
+    iterations).  cond_2(L) ~ ratio^{-1/2}."""
+    m = max(n // 2, 1)
+    g = rng(seed)
+    G = g.standard_normal(size=(n, m))
+    A = G @ G.T
+    A *= 1.0 / m
+    v = g.standard_normal(size=n)
+    lam = 0.0
+    for _ in range(50):
+        w = A @ v
+        lam = float(np.linalg.norm(w))
+        v = w / lam
+    A[np.arange(n), np.arange(n)] += ratio * lam
+    L = np.linalg.cholesky(A)
+    return _fill_upper(np.ascontiguousarray(L), upper)
+
+
+# ---- closed-form matrices (pins) -------------------------------------------
+
+def identity(n: int) -> np.ndarray:
+    return np.eye(n)
+
+
+def diagonal(n: int, seed: int) -> np.ndarray:
+    d = rng(seed).uniform(0.5, 4.0, size=n)
+    return np.diag(d)
+
+
+def bidiagonal_minus_one(n: int) -> np.ndarray:
+    """Unit lower bidiagonal with -1 on the subdiagonal.  Its inverse is the
+    all-ones lower triangle, so X is the column-wise prefix sum of B."""
+    L = np.eye(n)
+    if n > 1:
+        L[np.arange(1, n), np.arange(n - 1)] = -1.0
+    return L
+
+
+def ones_lower(n: int) -> np.ndarray:
+    """All-ones lower triangle.  Its inverse is unit lower bidiagonal with -1
+    on the subdiagonal, so X_i = B_i - B_{i-1}."""
+    return np.tril(np.ones((n, n)))
+
+
+def int_unit_lower(n: int, seed: int, density: float = 0.5) -> np.ndarray:
+    """Unit lower-triangular matrix with strict-lower entries in {-1, 0, 1}.
+    det = 1, so the inverse is an integer matrix."""
+    g = rng(seed)
+    vals = g.choice(np.array([-1.0, 0.0, 1.0]), size=(n, n),
+                    p=[density / 2, 1.0 - density, density / 2])
+    L = np.tril(vals, -1)
+    L[np.arange(n), np.arange(n)] = 1.0
+    return L
+
+
+def int_rhs(n: int, k: int, seed: int, lo: int = -8, hi: int = 8) -> np.ndarray:
+    return rng(seed + 77).integers(lo, hi + 1, size=(n, k)).astype(np.float64)
+
+
+# ---- serving mix -----------------------------------------------------------
+
+def log_uniform_int(g: np.random.Generator, lo: int, hi: int, size=None):
+    """round(exp(U(ln lo, ln hi))) clamped to [lo, hi]."""
+    u = g.uniform(math.log(lo), math.log(hi), size=size)
+    v = np.rint(np.exp(u)).astype(np.int64)
+    return np.clip(v, lo, hi)
+
+
+def serving_factor_sizes(count: int, seed: int, nmin: int = 64,
+                         nmax: int = 4096) -> np.ndarray:
+    return log_uniform_int(rng(seed), nmin, nmax, size=count)
+
+
+@dataclass
+class Request:
+    t_arrival: float   # seconds after the stream starts
+    factor: int        # index of the resident L
+    k: int             # number of right-hand sides
+    seed: int          # seed of its B
+
+
+def request_stream(num: int, rate_hz: float, num_factors: int, seed: int,
+                   kmin: int = 1, kmax: int = 512) -> List[Request]:
+    """Poisson arrivals (exponential gaps with mean 1/rate), each request
+    picks its factor uniformly and k log-uniform in [kmin, kmax]."""
+    g = rng(seed + 991)
+    gaps = g.exponential(1.0 / rate_hz, size=num)
+    t = np.cumsum(gaps)
+    fac = g.integers(0, num_factors, size=num)
+    ks = log_uniform_int(g, kmin, kmax, size=num)
+    return [Request(float(t[i]), int(fac[i]), int(ks[i]), seed * 1000003 + i)
+            for i in range(num)]
