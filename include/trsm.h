@@ -1,0 +1,176 @@
+/*
+ * trsm.h -- C ABI of the MI355X (gfx950) inversion-based triangular solver.
+ *
+ * Problem (Sec. I of Wicky, Solomonik & Hoefler, "Communication-Avoiding
+ * Parallel Algorithms for Solving Triangular Systems of Linear Equations"):
+ * given a lower-triangular n x n matrix L and a dense n x k matrix B, find the
+ * dense n x k matrix X with  L X = B.  Left side, lower triangle, no
+ * transpose, non-unit diagonal, no scaling factor.
+ *
+ * Method (Sec. VI, Alg. Diagonal-Inverter and Alg. It-Inv-TRSM): the n0 x n0
+ * diagonal blocks L(S_i, S_i), S_i = i*n0 : (i+1)*n0, are inverted by
+ * recursive triangular inversion (Sec. V, Alg. RecTriInv: invert both halves,
+ * then Linv21 = -(Linv22 L21) Linv11), and a blocked forward sweep then runs
+ * only dense matrix products:
+ *     X(S_i)      = Linv(S_i,S_i) * B'(S_i)
+ *     B'(T_{i+1}) = B'(T_{i+1}) - L(T_{i+1}, S_i) * X(S_i),   T_i = i*n0 : n.
+ * Everything runs on one GPU.
+ *
+ * Conventions shared by every call:
+ *  - Storage is row-major (C order) with leading dimensions in elements:
+ *    element (i,j) of L is L[i*ldl + j], (i,c) of B is B[i*ldb + c], of X is
+ *    X[i*ldx + c].  ldl >= n, ldb >= k, ldx >= k.  Only the lower triangle of
+ *    L (diagonal included) is ever read.
+ *  - Matrix pointers are DEVICE pointers unless stated.  The caller owns all
+ *    of them.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Calls marked "asynchronous" only enqueue work on `stream`.
+ *  - Element types follow the plan's precision: TRSM_F64 and the mixed modes
+ *    use binary64 L, B, X; TRSM_F32 uses binary32 L, B, X.
+ *  - No call throws; every call returns a trsm_status.  A plan is not
+ *    thread-safe; distinct plans may be used from distinct threads.
+ */
+#ifndef TRSM_MI355X_H
+#define TRSM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum trsm_status {
+  TRSM_OK = 0,
+  TRSM_EINVAL = 1,         /* bad size, leading dimension, pointer or option */
+  TRSM_ESINGULAR = 2,      /* a diagonal entry of L is zero or not finite */
+  TRSM_ENOMEM = 3,         /* a device allocation failed or a budget is too small */
+  TRSM_EHIP = 4,           /* the HIP runtime reported an error (see trsm_last_hip_error) */
+  TRSM_ENOTCONVERGED = 5,  /* refinement hit its iteration cap; X holds the best iterate */
+  TRSM_EBUSY = 6           /* serving: no free slot and queuing was refused */
+} trsm_status;
+
+typedef enum trsm_precision {
+  TRSM_F64 = 0,            /* binary64 everywhere (FP64 matrix cores) */
+  TRSM_F32 = 1,            /* binary32 inputs/outputs (FP32 matrix cores); blocks inverted in binary64 */
+  TRSM_MIXED_BF16 = 2,     /* binary64 in/out; sweep products in bfloat16 -> binary32,
+                              residual in binary64, iterative refinement */
+  TRSM_MIXED_F16 = 3       /* as above with IEEE half (power-of-two row scaling) */
+} trsm_precision;
+
+/* Plan flags. */
+#define TRSM_FLAG_NO_REFINE   0x1u  /* mixed modes: return the unrefined low-precision solve */
+#define TRSM_FLAG_RECURSIVE   0x2u  /* solve with the recursive baseline (Alg. Rec-TRSM order) */
+
+typedef struct trsm_plan_s* trsm_plan_t;
+
+typedef struct trsm_plan_info {
+  int64_t n, k;            /* problem sizes the plan was made for */
+  int64_t n0;              /* diagonal block size used (a power of two) */
+  int64_t m;               /* number of diagonal blocks, ceil(n / n0) */
+  int64_t leaf;            /* size of the blocks inverted directly in LDS */
+  int64_t n0_paper_rule;   /* the Sec. VIII rule evaluated at p = 1 (reported, not used) */
+  int32_t precision;       /* trsm_precision */
+  uint32_t flags;
+  size_t linv_bytes;       /* size of the Linv buffer trsm_invert_diag fills */
+  size_t workspace_bytes;  /* size of the workspace trsm_solve needs */
+  double inv_flops;        /* flops of the block inversion, n0^2 n / 3 (textbook count) */
+  double solve_flops;      /* n^2 k: the flops the metric credits */
+} trsm_plan_info;
+
+typedef struct trsm_info {
+  int32_t iterations;      /* refinement corrections applied (mixed modes), else 0 */
+  int32_t converged;       /* 1 if the refinement stopping test was met (or not needed) */
+  double backward_error;   /* last ||B - L X||_F / (||L||_F ||X||_F) measured, or -1 */
+  double correction;       /* last ||D||_F / ||X||_F (mixed modes), or -1 */
+  double unrefined_error;  /* mixed: ||X0 - X||_F / ||X||_F of the first low-precision
+                              solve against the returned X, or -1 */
+} trsm_info;
+
+/* Human-readable name of a status code (static string). */
+const char* trsm_status_string(trsm_status s);
+
+/* The last HIP error code seen by the library in this thread (0 = none). */
+int trsm_last_hip_error(void);
+
+/*
+ * trsm_plan -- choose the blocking for an n x n L and n x k B (host only).
+ *  n >= 0, k >= 0.  n0 = 0 picks the block size automatically (a cost model
+ *  of one GPU seeded by the Sec. VIII regime rule, rounded to a power of two);
+ *  otherwise n0 must be a power of two >= 1 (n0 >= n means the full inversion
+ *  approach, m = 1).  Returns TRSM_EINVAL for bad arguments, TRSM_ENOMEM if
+ *  the plan object cannot be allocated.  *out receives a new plan, owned by
+ *  the caller until trsm_plan_destroy.  A plan owns host metadata and, from
+ *  its first trsm_invert_diag on, one device status word (8 bytes) on the
+ *  device that was current then.
+ */
+trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0,
+                      uint32_t flags, trsm_plan_t* out);
+
+/* Fill *info with the plan's choices and buffer sizes (host only). */
+trsm_status trsm_plan_get_info(trsm_plan_t plan, trsm_plan_info* info);
+
+/* Release a plan (host only).  NULL is accepted. */
+trsm_status trsm_plan_destroy(trsm_plan_t plan);
+
+/*
+ * trsm_invert_diag -- Alg. Diagonal-Inverter (Sec. VI-A) with Alg. RecTriInv
+ * (Sec. V) for every block: fills `Linv` (device, linv_bytes from the plan,
+ * 256-byte aligned) with the inverses of the m diagonal n0 x n0 blocks of L,
+ * block b at Linv + b*n0*n0 binary64 values, row-major, zeros above the
+ * diagonal; a ragged last block (n0 not dividing n) is padded with the
+ * identity.  Mixed and F32 plans also store lower-precision copies behind
+ * the binary64 inverses.  Asynchronous.  A zero or non-finite diagonal entry
+ * is recorded on the device; read it with trsm_plan_last_error after the
+ * stream has been synchronised.  Returns TRSM_EINVAL for null pointers or
+ * ldl < n.
+ */
+trsm_status trsm_invert_diag(trsm_plan_t plan, const void* L, int64_t ldl, void* Linv,
+                             void* stream);
+
+/*
+ * After synchronising the stream used by trsm_invert_diag: *status is
+ * TRSM_ESINGULAR and *index the first row with a zero or non-finite
+ * diagonal entry, or TRSM_OK and -1.  Blocking (reads one device word).
+ */
+trsm_status trsm_plan_last_error(trsm_plan_t plan, trsm_status* status, int64_t* index);
+
+/*
+ * trsm_solve -- X = L^{-1} B by the blocked sweep of Alg. It-Inv-TRSM.
+ *  L, B, X: device matrices of the plan's element type; Linv: the buffer
+ *  filled by trsm_invert_diag with the same plan and the same L;
+ *  workspace: workspace_bytes of device memory (256-byte aligned).
+ *  X may be the same buffer as B when ldx == ldb (solve in place); any
+ *  other overlap is TRSM_EINVAL.
+ *  F64/F32 plans: asynchronous; `info` (nullable) receives iterations = 0.
+ *  Mixed plans: iterative refinement (low-precision sweep, binary64
+ *  residual B - L X, correction) until ||D||_F/||X||_F <= 1e-13 or the
+ *  backward error is <= 4u; this reads two norms back to the host per
+ *  iteration, so the call returns after the solve has finished.  Returns
+ *  TRSM_ENOTCONVERGED after 10 corrections.
+ *  With TRSM_FLAG_RECURSIVE the plan solves by the recursive baseline
+ *  (Alg. Rec-TRSM order: X1 = solve(L11, B1); B2 -= L21 X1; X2 = solve(L22,
+ *  B2), substitution at the leaves, no inversion) and Linv may be NULL.
+ */
+trsm_status trsm_solve(trsm_plan_t plan, const void* L, int64_t ldl, const void* Linv,
+                       const void* B, int64_t ldb, void* X, int64_t ldx, void* workspace,
+                       void* stream, trsm_info* info);
+
+/*
+ * trsm_residual -- R = B - L X in binary64 on the matrix cores, followed by
+ * deterministic reductions: norms[0] = ||R||_F, norms[1] = ||X||_F,
+ * norms[2] = max |R|.  The defect of the postcondition B = L X of Alg.
+ * It-Inv-TRSM.  L, X, B, R: device binary64; R may not overlap the inputs.
+ * `norms` is a HOST array of 3 doubles; the call synchronises the stream.
+ * workspace: at least trsm_residual_workspace_bytes(n, k) device bytes.
+ */
+size_t trsm_residual_workspace_bytes(int64_t n, int64_t k);
+trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl,
+                          const double* X, int64_t ldx, const double* B, int64_t ldb,
+                          double* R, int64_t ldr, void* workspace, double* norms,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRSM_MI355X_H */

@@ -1,0 +1,78 @@
+// Shared device/host helpers for the gfx950 triangular-solve kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace trsm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+typedef __bf16 bf16_t;
+typedef _Float16 f16_t;
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Matrix-core traits.  Every 16x16 output tile is produced by the 16x16xK
+// MFMA of the element type; lane l of a wave holds output rows
+// 4*(l/16) + r (r = 0..3) of column l%16.  The reduction index a lane feeds
+// is picked by the kernel (any permutation of k, used consistently for both
+// operands, gives the same sum up to rounding order).
+// ---------------------------------------------------------------------------
+template <typename T> struct Mfma;
+
+template <> struct Mfma<double> {
+  using Acc = double;
+  using Frag = double;   // one element per lane
+  using Out = d4;
+  static constexpr int kPerLane = 1;   // k values per lane per instruction
+  static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <> struct Mfma<float> {
+  using Acc = float;
+  using Frag = float;
+  using Out = f4;
+  static constexpr int kPerLane = 1;
+  static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <> struct Mfma<bf16_t> {
+  using Acc = float;
+  using Frag = bf16x8;
+  using Out = f4;
+  static constexpr int kPerLane = 8;
+  static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <> struct Mfma<f16_t> {
+  using Acc = float;
+  using Frag = f16x8;
+  using Out = f4;
+  static constexpr int kPerLane = 8;
+  static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename To, typename From>
+__device__ __forceinline__ To cvt(From v) { return static_cast<To>(v); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, float>(float v) { return static_cast<bf16_t>(v); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double v) { return static_cast<bf16_t>(static_cast<float>(v)); }
+template <> __device__ __forceinline__ f16_t cvt<f16_t, double>(double v) { return static_cast<f16_t>(static_cast<float>(v)); }
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace trsm

@@ -1,0 +1,336 @@
+// Tiled matrix-core GEMM for gfx950, the workhorse of every dense product on
+// the solve path: the diagonal-block apply X(S_i) = Linv_ii * B'(S_i) and the
+// trailing update B'(T_{i+1}) -= L(T_{i+1}, S_i) X(S_i) of Alg. It-Inv-TRSM,
+// the two products of each Alg. RecTriInv combine level, the recursive
+// baseline's off-diagonal update, and the residual B - L X.
+//
+//   Cout = beta * Cin + alpha * rowscale .* (op(A) * op(B))        (per batch)
+//
+// * A is M x K row-major (k contiguous).  B is K x N row-major (n contiguous)
+//   or, with BKMAJOR, stored N x K (k contiguous).  Both are staged through
+//   LDS k-contiguous, so every lane reads 32 contiguous bytes of a row.
+// * G_A_LOWER: A is lower triangular (A[i][k] = 0 for k > i).  Whole tiles
+//   past the diagonal are skipped and the diagonal tile is masked, so
+//   whatever is stored above A's diagonal is never used.
+// * G_B_LOWER: B is lower triangular (B[k][j] = 0 for k < j), same treatment.
+// * Optional second output C2 (another precision, optionally transposed,
+//   optionally scaled) feeds a following low-precision product.
+// * Batches: z -> offset (z / zdiv) * outer + (z % zdiv) * inner.
+//
+// Work decomposition: a workgroup of WGM x WGN waves owns a BM x BN tile;
+// each wave owns (BM/WGM) x (BN/WGN) made of 16x16 MFMA tiles.  K advances in
+// chunks of BK with two LDS buffers and a register prefetch of the next
+// chunk, one barrier per chunk.  Workgroup ids are remapped so that
+// consecutive tiles share an XCD (and its L2), in groups of GROUP_M row tiles.
+#pragma once
+
+#include "common.hpp"
+
+namespace trsm {
+
+enum GemmFlags : uint32_t {
+  G_A_LOWER = 1u,
+  G_B_LOWER = 2u,
+  G_C2_T = 4u,       // C2 stored transposed: C2[col * ldc2 + row]
+  G_BETA = 8u,       // read Cin
+  G_ROWSCALE = 16u,  // multiply the product by rscale[row * ld_rs]
+};
+
+template <typename TIn, typename TCin, typename TCout, typename TC2>
+struct GemmParams {
+  const TIn* A; int64_t lda; int64_t sa_o, sa_i;
+  const TIn* B; int64_t ldb; int64_t sb_o, sb_i;
+  const TCin* Cin; int64_t ldci; int64_t sci_o, sci_i;
+  TCout* Cout; int64_t ldco; int64_t sco_o, sco_i;
+  TC2* C2; int64_t ldc2;
+  const float* rscale; int64_t ld_rs;
+  int M, N, K;
+  int zdiv;
+  double alpha, beta;
+  float c2scale;
+  uint32_t flags;
+};
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { typedef double T2 __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float> { typedef float T2 __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<bf16_t> { typedef __bf16 T2 __attribute__((ext_vector_type(8))); };
+template <> struct VecOf<f16_t> { typedef _Float16 T2 __attribute__((ext_vector_type(8))); };
+
+template <typename TIn, typename TCin, typename TCout, typename TC2,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+__global__ __launch_bounds__(WGM * WGN * 64)
+void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
+  using MF = Mfma<TIn>;
+  using Acc = typename MF::Acc;
+  using Out = typename MF::Out;
+  using V16 = typename VecOf<TIn>::T2;          // 16-byte vector of TIn
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int VEC = 16 / sizeof(TIn);         // elements per 16-byte vector
+  constexpr int BK = 128 / sizeof(TIn);         // one 128-byte row segment per chunk
+  constexpr int KL = BK / 4;                    // contiguous k per lane per chunk
+  constexpr int STEPS = KL / MF::kPerLane;      // MFMAs per 16x16 tile per chunk
+  constexpr int LDS_S = BK + VEC;               // padded LDS row stride (elements)
+  constexpr int WTM = BM / WGM, WTN = BN / WGN; // wave tile
+  constexpr int TM = WTM / 16, TN = WTN / 16;   // MFMA tiles per wave
+  constexpr int VPR = BK / VEC;                 // vectors per k-row segment
+  constexpr int A_ITERS = BM * VPR / NT;
+  constexpr int B_ITERS = BN * VPR / NT;
+  static_assert(A_ITERS * NT == BM * VPR, "A tile load must divide evenly");
+  static_assert(B_ITERS * NT == BN * VPR, "B tile load must divide evenly");
+  constexpr int GROUP_M = 8;
+
+  __shared__ __attribute__((aligned(16))) TIn As[2][BM * LDS_S];
+  __shared__ __attribute__((aligned(16))) TIn Bs[2][BN * LDS_S];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int gi = lane & 15, g = lane >> 4;
+
+  // ---- batch offsets --------------------------------------------------
+  const int z = blockIdx.z;
+  const int zo = z / p.zdiv, zi = z % p.zdiv;
+  const TIn* __restrict__ A = p.A + zo * p.sa_o + zi * p.sa_i;
+  const TIn* __restrict__ B = p.B + zo * p.sb_o + zi * p.sb_i;
+  const int M = p.M, N = p.N, K = p.K;
+
+  // ---- tile coordinates (XCD-aware, grouped) -----------------------------
+  const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+  int bid = blockIdx.x;
+  const int nwg = gridDim.x;
+  if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  const int per_group = GROUP_M * ntn;
+  const int grp = bid / per_group;
+  const int first_m = grp * GROUP_M;
+  const int gsize = min(ntm - first_m, GROUP_M);
+  const int in_grp = bid % per_group;
+  const int tm = first_m + in_grp % gsize;
+  const int tn = in_grp / gsize;
+  const int r0 = tm * BM, c0 = tn * BN;
+
+  const bool a_lower = p.flags & G_A_LOWER;
+  const bool b_lower = p.flags & G_B_LOWER;
+  int kbeg = 0, kend = K;
+  if (a_lower) kend = min(K, r0 + BM);
+  if (b_lower) kbeg = (min(c0, K) / BK) * BK;
+  const int nchunks = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  Out acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = Acc(0);
+
+  // ---- global -> register staging --------------------------------------
+  V16 ra[A_ITERS], rb[B_ITERS];
+
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < A_ITERS; ++it) {
+      const int idx = tid + it * NT;
+      const int row = idx / VPR, kv = (idx % VPR) * VEC;
+      const int gr = r0 + row, gk = k0 + kv;
+      V16 v;
+      if (ALIGNED && gr < M && gk + VEC <= K) {
+        v = *reinterpret_cast<const V16*>(A + (int64_t)gr * p.lda + gk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          v[e] = (gr < M && gk + e < K) ? A[(int64_t)gr * p.lda + gk + e] : TIn(0);
+      }
+      if (a_lower) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (gk + e > gr) v[e] = TIn(0);
+      }
+      ra[it] = v;
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < B_ITERS; ++it) {
+      const int idx = tid + it * NT;
+      V16 v;
+      if constexpr (BKMAJOR) {
+        // B stored N x K: a row of the stored matrix is a column of B.
+        const int col = idx / VPR, kv = (idx % VPR) * VEC;
+        const int gc = c0 + col, gk = k0 + kv;
+        if (ALIGNED && gc < N && gk + VEC <= K) {
+          v = *reinterpret_cast<const V16*>(B + (int64_t)gc * p.ldb + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            v[e] = (gc < N && gk + e < K) ? B[(int64_t)gc * p.ldb + gk + e] : TIn(0);
+        }
+        if (b_lower) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (gk + e < gc) v[e] = TIn(0);
+        }
+      } else {
+        // B stored K x N: vectors run along n; (BK rows) x (BN/VEC vectors).
+        constexpr int VPC = BN / VEC;
+        const int krow = idx / VPC, cv = (idx % VPC) * VEC;
+        const int gk = k0 + krow, gc = c0 + cv;
+        if (ALIGNED && gk < K && gc + VEC <= N) {
+          v = *reinterpret_cast<const V16*>(B + (int64_t)gk * p.ldb + gc);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            v[e] = (gk < K && gc + e < N) ? B[(int64_t)gk * p.ldb + gc + e] : TIn(0);
+        }
+        if (b_lower) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (gk < gc + e) v[e] = TIn(0);
+        }
+      }
+      rb[it] = v;
+    }
+  };
+  auto store_ab = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < A_ITERS; ++it) {
+      const int idx = tid + it * NT;
+      const int row = idx / VPR, kv = (idx % VPR) * VEC;
+      *reinterpret_cast<V16*>(&As[buf][row * LDS_S + kv]) = ra[it];
+    }
+#pragma unroll
+    for (int it = 0; it < B_ITERS; ++it) {
+      const int idx = tid + it * NT;
+      if constexpr (BKMAJOR) {
+        const int col = idx / VPR, kv = (idx % VPR) * VEC;
+        *reinterpret_cast<V16*>(&Bs[buf][col * LDS_S + kv]) = rb[it];
+      } else {
+        constexpr int VPC = BN / VEC;
+        const int krow = idx / VPC, cv = (idx % VPC) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) Bs[buf][(cv + e) * LDS_S + krow] = rb[it][e];
+      }
+    }
+  };
+
+  // ---- main loop --------------------------------------------------------
+  if (nchunks > 0) {
+    load_a(kbeg);
+    load_b(kbeg);
+    store_ab(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const int buf = c & 1;
+      const bool more = c + 1 < nchunks;
+      if (more) {
+        load_a(kbeg + (c + 1) * BK);
+        load_b(kbeg + (c + 1) * BK);
+      }
+      // fragments: lane group g owns k = g*KL .. g*KL+KL-1 of the chunk
+      V16 fa[TM][2], fb[TN][2];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const TIn* src = &As[buf][(wm * WTM + i * 16 + gi) * LDS_S + g * KL];
+        fa[i][0] = *reinterpret_cast<const V16*>(src);
+        fa[i][1] = *reinterpret_cast<const V16*>(src + VEC);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const TIn* src = &Bs[buf][(wn * WTN + j * 16 + gi) * LDS_S + g * KL];
+        fb[j][0] = *reinterpret_cast<const V16*>(src);
+        fb[j][1] = *reinterpret_cast<const V16*>(src + VEC);
+      }
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          typename MF::Frag a;
+          if constexpr (MF::kPerLane == 1) {
+            a = fa[i][s / VEC][s % VEC];
+          } else {
+            a = fa[i][s];
+          }
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            typename MF::Frag b;
+            if constexpr (MF::kPerLane == 1) {
+              b = fb[j][s / VEC][s % VEC];
+            } else {
+              b = fb[j][s];
+            }
+            acc[i][j] = MF::mma(a, b, acc[i][j]);
+          }
+        }
+      }
+      if (more) store_ab(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue ---------------------------------------------------------
+  TCout* __restrict__ Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
+  const TCin* __restrict__ Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
+  const bool use_beta = (p.flags & G_BETA) && Ci;
+  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
+  const bool c2t = p.flags & G_C2_T;
+  const Acc alpha = static_cast<Acc>(p.alpha);
+  const Acc beta = static_cast<Acc>(p.beta);
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + wm * WTM + i * 16 + g * 4 + r;
+      if (row >= M) continue;
+      Acc rs = Acc(1);
+      if (use_rs) rs = static_cast<Acc>(p.rscale[(int64_t)row * p.ld_rs]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = c0 + wn * WTN + j * 16 + gi;
+        if (col >= N) continue;
+        Acc v = alpha * (acc[i][j][r] * rs);
+        if (use_beta) v += beta * static_cast<Acc>(Ci[(int64_t)row * p.ldci + col]);
+        Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
+        if (p.C2) {
+          const TC2 w = cvt<TC2>(v * static_cast<Acc>(p.c2scale));
+          if (c2t) p.C2[(int64_t)col * p.ldc2 + row] = w;
+          else p.C2[(int64_t)row * p.ldc2 + col] = w;
+        }
+      }
+    }
+  }
+}
+
+// Host-side launch helper.  Picks the aligned (16-byte vector) path when every
+// operand start, leading dimension and batch stride allows it.
+template <typename TIn, typename TCin, typename TCout, typename TC2,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR>
+inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int batch,
+                              hipStream_t stream) {
+  if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
+  constexpr int VEC = 16 / sizeof(TIn);
+  auto al = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
+  const bool aligned = al(p.A) && al(p.B) && p.lda % VEC == 0 && p.ldb % VEC == 0 &&
+                       p.sa_o % VEC == 0 && p.sa_i % VEC == 0 && p.sb_o % VEC == 0 &&
+                       p.sb_i % VEC == 0;
+  const int64_t tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
+  dim3 grid((unsigned)tiles, 1, (unsigned)batch);
+  dim3 block(WGM * WGN * 64);
+  if (aligned)
+    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, true><<<grid, block, 0, stream>>>(p);
+  else
+    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, false><<<grid, block, 0, stream>>>(p);
+  return hipGetLastError();
+}
+
+template <typename TIn, typename TCin, typename TCout, typename TC2>
+inline GemmParams<TIn, TCin, TCout, TC2> gemm_params() {
+  GemmParams<TIn, TCin, TCout, TC2> p{};
+  p.zdiv = 1;
+  p.alpha = 1.0;
+  p.beta = 0.0;
+  p.c2scale = 1.0f;
+  return p;
+}
+
+}  // namespace trsm

@@ -1,0 +1,345 @@
+// Non-GEMM kernels of the gfx950 triangular solver: diagonal-block
+// extraction, the LDS leaf of the recursive triangular inversion, the
+// substitution leaf of the recursive baseline, precision conversions and
+// deterministic norm reductions.
+#include "kernels.hpp"
+
+#include <math.h>
+
+namespace trsm {
+
+namespace {
+
+inline unsigned grid_for(int64_t work, int threads, int64_t cap = 1 << 20) {
+  int64_t g = (work + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. Diagonal-Inverter, data movement: the block diagonal L_D is copied
+// into its own packed buffer (one n0 x n0 binary64 block per S_i).
+// ---------------------------------------------------------------------------
+template <typename TL>
+__global__ void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl, int64_t n,
+                                    int64_t n0, int64_t m, double* __restrict__ Linv,
+                                    unsigned long long* bad) {
+  const int64_t per = n0 * n0;
+  const int64_t total = per * m;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / per, e = idx % per;
+    const int64_t i = e / n0, j = e % n0;
+    const int64_t gr = b * n0 + i, gc = b * n0 + j;
+    double v;
+    if (gr < n && gc < n) {
+      v = (j <= i) ? static_cast<double>(L[gr * ldl + gc]) : 0.0;
+      if (i == j && (!(v != 0.0) || !isfinite(v))) atomicMin(bad, (unsigned long long)gr);
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    Linv[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. RecTriInv base case ("sequential inversion"): the nb x nb leaf is
+// inverted by substitution on the identity.  Thread t owns column t of the
+// inverse: x[t][t] = 1 / l[t][t];  x[i][t] = -(sum_{p<i} l[i][p] x[p][t]) / l[i][i]
+// for i > t (entries above the diagonal of the inverse are zero).  All lanes
+// walk the same (i, p) so that l[i][p] is an LDS broadcast.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void trtri_leaf_kernel(double* __restrict__ Linv, int64_t n0,
+                                                        int64_t nb, int64_t lpb) {
+  __shared__ double Ls[64][65];
+  __shared__ double Xs[64][65];
+  const int64_t leaf = blockIdx.x;
+  const int64_t b = leaf / lpb, q = leaf % lpb;
+  double* P = Linv + b * n0 * n0 + q * nb * (n0 + 1);
+  const int t = threadIdx.x;
+  for (int i = 0; i < nb; ++i) {
+    Ls[i][t] = (t < nb && t <= i) ? P[(int64_t)i * n0 + t] : 0.0;
+    Xs[i][t] = 0.0;
+  }
+  __syncthreads();
+  if (t < nb) Xs[t][t] = 1.0 / Ls[t][t];
+  for (int i = 1; i < nb; ++i) {
+    if (t < i) {
+      double s = 0.0;
+      for (int p = 0; p < i; ++p) s += Ls[i][p] * Xs[p][t];
+      Xs[i][t] = -s / Ls[i][i];
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < nb; ++i)
+    if (t < nb && t <= i) P[(int64_t)i * n0 + t] = Xs[i][t];
+}
+
+__global__ void zero_upper_kernel(double* __restrict__ Linv, int64_t n0, int64_t m) {
+  const int64_t per = n0 * n0, total = per * m;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx % per;
+    if (e % n0 > e / n0) Linv[idx] = 0.0;
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void convert_kernel(const TI* __restrict__ in, TO* __restrict__ out, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = cvt<TO>(in[i]);
+}
+
+template <typename TI, typename TO>
+__global__ void copy2d_kernel(const TI* __restrict__ in, int64_t ldi, TO* __restrict__ out,
+                              int64_t ldo, int64_t rows, int64_t cols, double scale) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i % cols;
+    out[r * ldo + c] = cvt<TO>(static_cast<double>(in[r * ldi + c]) * scale);
+  }
+}
+
+__global__ void axpy_kernel(const float* __restrict__ D, int64_t ldd, double* __restrict__ X,
+                            int64_t ldx, int64_t rows, int64_t cols, double scale, int assign) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i % cols;
+    const double d = scale * static_cast<double>(D[r * ldd + c]);
+    if (assign) X[r * ldx + c] = d;
+    else X[r * ldx + c] += d;
+  }
+}
+
+// One wave per (row r, column block c).  Waves for c >= floor(r / n0) (the
+// diagonal block and beyond) only write a unit scale.
+template <typename TO>
+__global__ __launch_bounds__(256) void lowcopy_kernel(const double* __restrict__ L, int64_t ldl,
+                                                      int64_t n, int64_t n0, int64_t m,
+                                                      TO* __restrict__ Llow,
+                                                      float* __restrict__ rscale, float target) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wid >= n * m) return;
+  const int64_t r = wid / m, c = wid % m;
+  if (c >= r / n0) {
+    if (lane == 0) rscale[r * m + c] = 1.0f;
+    return;
+  }
+  const double* src = L + r * ldl + c * n0;
+  double mx = 0.0;
+  for (int64_t j = lane; j < n0; j += 64) mx = fmax(mx, fabs(src[j]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  int e = 0;
+  if (mx > 0.0) e = ilogb((double)target) - ilogb(mx) - 1;
+  TO* dst = Llow + r * n + c * n0;
+  for (int64_t j = lane; j < n0; j += 64) dst[j] = cvt<TO>(ldexp(src[j], e));
+  if (lane == 0) rscale[r * m + c] = ldexpf(1.0f, -e);
+}
+
+// Recursive baseline leaf: forward substitution, one thread per column.
+template <typename T>
+__global__ __launch_bounds__(64) void subst_leaf_kernel(const T* __restrict__ L, int64_t ldl,
+                                                        T* __restrict__ X, int64_t ldx,
+                                                        int64_t nb, int64_t k) {
+  __shared__ T Ls[64][65];
+  __shared__ T Xs[64][65];
+  const int t = threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x * 64 + t;
+  for (int i = 0; i < nb; ++i) Ls[i][t] = (t < nb && t <= i) ? L[(int64_t)i * ldl + t] : T(0);
+  __syncthreads();
+  if (c < k) {
+    for (int i = 0; i < nb; ++i) {
+      T s = X[(int64_t)i * ldx + c];
+      for (int p = 0; p < i; ++p) s -= Ls[i][p] * Xs[p][t];
+      const T x = s / Ls[i][i];
+      Xs[i][t] = x;
+      X[(int64_t)i * ldx + c] = x;
+    }
+  }
+}
+
+// Deterministic reductions: a fixed grid of kNormBlocks blocks, each thread
+// visiting a fixed set of elements in order, then a fixed-shape tree.
+__device__ inline void block_reduce2(double& s, double& mx) {
+  __shared__ double ss[256], sm[256];
+  const int t = threadIdx.x;
+  ss[t] = s;
+  sm[t] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      ss[t] = ss[t] + ss[t + w];
+      sm[t] = fmax(sm[t], sm[t + w]);
+    }
+    __syncthreads();
+  }
+  s = ss[0];
+  mx = sm[0];
+}
+
+__global__ __launch_bounds__(256) void sumsq_max_part(const double* __restrict__ A, int64_t lda,
+                                                      int64_t rows, int64_t cols,
+                                                      double* __restrict__ part) {
+  const int64_t total = rows * cols;
+  double s = 0.0, mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)kNormBlocks * 256) {
+    const double v = A[(i / cols) * lda + (i % cols)];
+    s += v * v;
+    mx = fmax(mx, fabs(v));
+  }
+  block_reduce2(s, mx);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    part[kNormBlocks + blockIdx.x] = mx;
+  }
+}
+
+template <typename TL>
+__global__ __launch_bounds__(256) void sumsq_lower_part(const TL* __restrict__ L, int64_t ldl,
+                                                        int64_t n, double* __restrict__ part) {
+  const int64_t total = n * n;
+  double s = 0.0, mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)kNormBlocks * 256) {
+    const int64_t r = i / n, c = i % n;
+    if (c <= r) {
+      const double v = static_cast<double>(L[r * ldl + c]);
+      s += v * v;
+      mx = fmax(mx, fabs(v));
+    }
+  }
+  block_reduce2(s, mx);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    part[kNormBlocks + blockIdx.x] = mx;
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  double s = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < kNormBlocks; i += 256) {
+    s += part[i];
+    mx = fmax(mx, part[kNormBlocks + i]);
+  }
+  block_reduce2(s, mx);
+  if (threadIdx.x == 0) {
+    out[0] = s;
+    out[1] = mx;
+  }
+}
+
+}  // namespace
+
+template <typename TL>
+hipError_t launch_extract_diag(const TL* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
+                               double* Linv, unsigned long long* bad, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  extract_diag_kernel<TL><<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(L, ldl, n, n0, m, Linv, bad);
+  return hipGetLastError();
+}
+template hipError_t launch_extract_diag<double>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                                double*, unsigned long long*, hipStream_t);
+template hipError_t launch_extract_diag<float>(const float*, int64_t, int64_t, int64_t, int64_t,
+                                               double*, unsigned long long*, hipStream_t);
+
+hipError_t launch_trtri_leaf(double* Linv, int64_t n0, int64_t m, int64_t nb, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t lpb = n0 / nb;
+  trtri_leaf_kernel<<<(unsigned)(m * lpb), 64, 0, s>>>(Linv, n0, nb, lpb);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_upper(double* Linv, int64_t n0, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  zero_upper_kernel<<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(Linv, n0, m);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI* in, TO* out, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  convert_kernel<TI, TO><<<grid_for(count, 256), 256, 0, s>>>(in, out, count);
+  return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+
+template <typename TI, typename TO>
+hipError_t launch_copy2d(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t rows,
+                         int64_t cols, double scale, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  copy2d_kernel<TI, TO><<<grid_for(rows * cols, 256), 256, 0, s>>>(in, ldi, out, ldo, rows, cols,
+                                                                   scale);
+  return hipGetLastError();
+}
+template hipError_t launch_copy2d<double, double>(const double*, int64_t, double*, int64_t,
+                                                  int64_t, int64_t, double, hipStream_t);
+template hipError_t launch_copy2d<float, float>(const float*, int64_t, float*, int64_t, int64_t,
+                                                int64_t, double, hipStream_t);
+template hipError_t launch_copy2d<double, float>(const double*, int64_t, float*, int64_t, int64_t,
+                                                 int64_t, double, hipStream_t);
+template hipError_t launch_copy2d<float, double>(const float*, int64_t, double*, int64_t, int64_t,
+                                                 int64_t, double, hipStream_t);
+
+hipError_t launch_axpy_f32_to_f64(const float* D, int64_t ldd, double* X, int64_t ldx,
+                                  int64_t rows, int64_t cols, double scale, bool assign,
+                                  hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  axpy_kernel<<<grid_for(rows * cols, 256), 256, 0, s>>>(D, ldd, X, ldx, rows, cols, scale,
+                                                         assign ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_lowcopy(const double* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
+                          TO* Llow, float* rscale, float target, hipStream_t s) {
+  if (n <= 0 || m <= 0) return hipSuccess;
+  const int64_t waves = n * m;
+  lowcopy_kernel<TO><<<grid_for(waves * 64, 256, INT64_MAX), 256, 0, s>>>(L, ldl, n, n0, m, Llow,
+                                                                          rscale, target);
+  return hipGetLastError();
+}
+template hipError_t launch_lowcopy<bf16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                           bf16_t*, float*, float, hipStream_t);
+template hipError_t launch_lowcopy<f16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                          f16_t*, float*, float, hipStream_t);
+
+template <typename T>
+hipError_t launch_subst_leaf(const T* L, int64_t ldl, T* X, int64_t ldx, int64_t nb, int64_t k,
+                             hipStream_t s) {
+  if (nb <= 0 || k <= 0) return hipSuccess;
+  subst_leaf_kernel<T><<<(unsigned)ceil_div(k, 64), 64, 0, s>>>(L, ldl, X, ldx, nb, k);
+  return hipGetLastError();
+}
+template hipError_t launch_subst_leaf<double>(const double*, int64_t, double*, int64_t, int64_t,
+                                              int64_t, hipStream_t);
+template hipError_t launch_subst_leaf<float>(const float*, int64_t, float*, int64_t, int64_t,
+                                             int64_t, hipStream_t);
+
+hipError_t launch_sumsq_max(const double* A, int64_t lda, int64_t rows, int64_t cols,
+                            double* part, double* out, hipStream_t s) {
+  sumsq_max_part<<<kNormBlocks, 256, 0, s>>>(A, lda, rows, cols, part);
+  reduce_final<<<1, 256, 0, s>>>(part, out);
+  return hipGetLastError();
+}
+
+template <typename TL>
+hipError_t launch_sumsq_lower(const TL* L, int64_t ldl, int64_t n, double* part, double* out,
+                              hipStream_t s) {
+  sumsq_lower_part<TL><<<kNormBlocks, 256, 0, s>>>(L, ldl, n, part);
+  reduce_final<<<1, 256, 0, s>>>(part, out);
+  return hipGetLastError();
+}
+template hipError_t launch_sumsq_lower<double>(const double*, int64_t, int64_t, double*, double*,
+                                               hipStream_t);
+template hipError_t launch_sumsq_lower<float>(const float*, int64_t, int64_t, double*, double*,
+                                              hipStream_t);
+
+}  // namespace trsm

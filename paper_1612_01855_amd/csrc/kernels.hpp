@@ -1,0 +1,66 @@
+// Launchers of the non-GEMM kernels (defined in kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace trsm {
+
+// Copy the m diagonal n0 x n0 blocks of L (lower part, zeros above) into the
+// packed binary64 buffer Linv; positions past row/column n get the identity.
+// Records min(row) of any zero / non-finite diagonal entry in *bad.
+template <typename TL>
+hipError_t launch_extract_diag(const TL* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
+                               double* Linv, unsigned long long* bad, hipStream_t s);
+
+// Invert, in place, every nb x nb diagonal leaf of every packed block
+// (nb <= 64): column-oriented substitution on the identity in LDS.
+hipError_t launch_trtri_leaf(double* Linv, int64_t n0, int64_t m, int64_t nb, hipStream_t s);
+
+// Zero the strict upper triangle of every packed block.
+hipError_t launch_zero_upper(double* Linv, int64_t n0, int64_t m, hipStream_t s);
+
+// out[i] = (TO) in[i]
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI* in, TO* out, int64_t count, hipStream_t s);
+
+// Dense 2-D copy / convert with scaling: out[i*ldo+j] = (TO)(scale * in[i*ldi+j]).
+template <typename TI, typename TO>
+hipError_t launch_copy2d(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t rows,
+                         int64_t cols, double scale, hipStream_t s);
+
+// X[i*ldx+j] += scale * D[i*ldd+j]  (binary64 X, binary32 D), or X = scale*D
+// when `assign`.
+hipError_t launch_axpy_f32_to_f64(const float* D, int64_t ldd, double* X, int64_t ldx,
+                                  int64_t rows, int64_t cols, double scale, bool assign,
+                                  hipStream_t s);
+
+// Low-precision copy of the strictly-lower off-diagonal blocks of L:
+// Llow[r*n + c] = l[r][c] * 2^e(r, blk) for c < n0*floor(r/n0), with one
+// power-of-two scale per (row, column block) chosen from the row segment's
+// largest magnitude (target: largest magnitude near `target`), and
+// rscale[r*m + blk] = 2^-e (exact inverse scale).
+template <typename TO>
+hipError_t launch_lowcopy(const double* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
+                          TO* Llow, float* rscale, float target, hipStream_t s);
+
+// Forward substitution on an nb x nb lower-triangular leaf (nb <= 64) for k
+// right-hand-side columns, in place on X: the recursive baseline's base case
+// (no inversion).  One thread per column.
+template <typename T>
+hipError_t launch_subst_leaf(const T* L, int64_t ldl, T* X, int64_t ldx, int64_t nb,
+                             int64_t k, hipStream_t s);
+
+// Deterministic reductions of a binary64 n x k matrix (fixed block split,
+// fixed order): partial sums of squares and maxima into `part` (device,
+// 2 * kNormBlocks doubles), then the final values into out[0] = sum of
+// squares, out[1] = max |a|.
+constexpr int kNormBlocks = 1024;
+hipError_t launch_sumsq_max(const double* A, int64_t lda, int64_t rows, int64_t cols,
+                            double* part, double* out, hipStream_t s);
+
+// Frobenius norm squared of the lower triangle of L into out[0] (deterministic).
+template <typename TL>
+hipError_t launch_sumsq_lower(const TL* L, int64_t ldl, int64_t n, double* part, double* out,
+                              hipStream_t s);
+
+}  // namespace trsm

@@ -1,0 +1,652 @@
+// Host runtime and C ABI of the gfx950 inversion-based triangular solver.
+//
+// trsm_plan        : block size n0 and buffer layout (Sec. VIII rule reported,
+//                    a one-GPU cost model chooses).
+// trsm_invert_diag : Alg. Diagonal-Inverter with Alg. RecTriInv per block.
+// trsm_solve       : the blocked forward sweep of Alg. It-Inv-TRSM
+//                    (right-looking with the deferred update of B), the
+//                    recursive baseline (Alg. Rec-TRSM order), or the mixed
+//                    precision sweep with iterative refinement.
+// trsm_residual    : B - L X in binary64 plus deterministic norms.
+#include "../../include/trsm.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "common.hpp"
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+using namespace trsm;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+inline trsm_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return TRSM_EHIP;
+}
+
+#define TRSM_HIP(...)                           \
+  do {                                          \
+    hipError_t e_ = (__VA_ARGS__);              \
+    if (e_ != hipSuccess) return hip_fail(e_);  \
+  } while (0)
+
+#define TRSM_TRY(...)                           \
+  do {                                          \
+    trsm_status s_ = (__VA_ARGS__);             \
+    if (s_ != TRSM_OK) return s_;               \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+inline int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+inline int64_t prev_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p * 2 <= v) p <<= 1;
+  return p;
+}
+
+inline size_t elem_size(trsm_precision p) { return p == TRSM_F32 ? 4 : 8; }
+inline bool is_mixed(trsm_precision p) { return p == TRSM_MIXED_BF16 || p == TRSM_MIXED_F16; }
+
+}  // namespace
+
+struct trsm_plan_s {
+  int64_t n = 0, k = 0, n0 = 1, m = 0, leaf = 1, n0_paper = 1;
+  trsm_precision prec = TRSM_F64;
+  uint32_t flags = 0;
+  // Linv buffer layout (byte offsets)
+  size_t off_linv64 = 0, off_linv32 = 0, off_llow = 0, off_rscale = 0, off_lnorm = 0, off_lpart = 0;
+  size_t linv_bytes = 0;
+  // workspace layout (byte offsets)
+  size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_part = 0, ws_norm = 0;
+  size_t ws_bytes = 0;
+  unsigned long long* d_bad = nullptr;   // first singular row (device word)
+};
+
+// ---------------------------------------------------------------------------
+// A0: choice of n0.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Sec. VIII regime rule at p = 1: n < 4k -> one large dimension, n0 = n;
+// n > 4k -> two large dimensions, n0 = (n k^3)^{1/4}; n = 4k -> three large
+// dimensions, n0 = min(sqrt(n k), n).
+int64_t paper_rule_n0(int64_t n, int64_t k) {
+  if (n <= 0) return 1;
+  double v;
+  if (n < 4 * k) v = (double)n;
+  else if (n > 4 * k) v = pow((double)n * (double)k * (double)k * (double)k, 0.25);
+  else v = fmin(sqrt((double)n * (double)k), (double)n);
+  if (v < 1) v = 1;
+  return (int64_t)llround(v);
+}
+
+// One-GPU reading of the alpha-beta-gamma model (Sec. II-A): the sweep's n^2 k
+// flops do not depend on n0; the inversion adds n n0^2 / 3 flops, and each of
+// the ceil(n/n0) dependent steps costs a fixed synchronisation time.
+int64_t auto_n0(int64_t n, int64_t k, trsm_precision prec) {
+  if (n <= 16) return next_pow2(n < 1 ? 1 : n);
+  const double rate = (prec == TRSM_F32) ? 90e12 : 45e12;  // sustained matrix-core rate
+  const double t_step = 12e-6;                             // per dependent step
+  const double t_level = 10e-6;                            // per inversion level
+  int64_t best = 16;
+  double best_t = 1e300;
+  const int64_t top = next_pow2(n);
+  for (int64_t n0 = 16; n0 <= top; n0 <<= 1) {
+    const double m = ceil((double)n / (double)n0);
+    const double levels = n0 > 64 ? log2((double)n0 / 64.0) : 0.0;
+    const double t = (double)n * n0 * n0 / 3.0 / rate + levels * t_level + m * t_step;
+    (void)k;
+    if (t < best_t) {
+      best_t = t;
+      best = n0;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// GEMM front-ends (tile shapes per element type).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+struct Gemm {
+  using P = GemmParams<T, T, T, float>;
+  static hipError_t run(const P& p, int batch, hipStream_t s) {
+    return launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s);
+  }
+};
+
+// C[M x N] = beta*C + alpha * op(A) * op(B), row-major, no batching.
+template <typename T>
+hipError_t gemm_simple(const T* A, int64_t lda, const T* B, int64_t ldb, const T* Cin,
+                       int64_t ldci, T* Cout, int64_t ldco, int64_t M, int64_t N, int64_t K,
+                       double alpha, double beta, uint32_t flags, hipStream_t s) {
+  auto p = gemm_params<T, T, T, float>();
+  p.A = A; p.lda = lda;
+  p.B = B; p.ldb = ldb;
+  p.Cin = Cin; p.ldci = ldci;
+  p.Cout = Cout; p.ldco = ldco;
+  p.M = (int)M; p.N = (int)N; p.K = (int)K;
+  p.alpha = alpha; p.beta = beta;
+  p.flags = flags | (Cin ? G_BETA : 0u);
+  return Gemm<T>::run(p, 1, s);
+}
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + abytes, b0 = (uintptr_t)b, b1 = b0 + bbytes;
+  return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// A1: Alg. Diagonal-Inverter / Alg. RecTriInv.
+// ---------------------------------------------------------------------------
+namespace {
+
+// All levels of the recursive inversion, batched over every pair of every
+// block.  At level h the pair [[A11, 0], [A21, A22]] (2h x 2h, A11 and A22
+// already inverted) is completed with
+//     T   = A22^{-1} A21          (stored in the pair's unused upper-right)
+//     A21 = -T A11^{-1}
+// which is Alg. RecTriInv's combine, -(Linv22 L21) Linv11, in the paper's
+// association order.
+hipError_t rec_tri_inv_levels(double* Linv, int64_t n0, int64_t m, int64_t nb, hipStream_t s) {
+  for (int64_t h = nb; h < n0; h *= 2) {
+    const int64_t ppb = n0 / (2 * h);  // pairs per block
+    auto p = gemm_params<double, double, double, float>();
+    p.M = p.N = p.K = (int)h;
+    p.zdiv = (int)ppb;
+    // GEMM 1: T = A22inv * A21
+    p.A = Linv + h * n0 + h;  p.lda = n0;  p.sa_o = n0 * n0;  p.sa_i = 2 * h * (n0 + 1);
+    p.B = Linv + h * n0;      p.ldb = n0;  p.sb_o = n0 * n0;  p.sb_i = 2 * h * (n0 + 1);
+    p.Cout = Linv + h;        p.ldco = n0; p.sco_o = n0 * n0; p.sco_i = 2 * h * (n0 + 1);
+    p.flags = G_A_LOWER;
+    p.alpha = 1.0;
+    hipError_t e = Gemm<double>::run(p, (int)(m * ppb), s);
+    if (e != hipSuccess) return e;
+    // GEMM 2: A21 = -T * A11inv
+    p.A = Linv + h;           p.lda = n0;  p.sa_o = n0 * n0;  p.sa_i = 2 * h * (n0 + 1);
+    p.B = Linv;               p.ldb = n0;  p.sb_o = n0 * n0;  p.sb_i = 2 * h * (n0 + 1);
+    p.Cout = Linv + h * n0;   p.ldco = n0; p.sco_o = n0 * n0; p.sco_i = 2 * h * (n0 + 1);
+    p.flags = G_B_LOWER;
+    p.alpha = -1.0;
+    e = Gemm<double>::run(p, (int)(m * ppb), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// A2/A3: the blocked sweep of Alg. It-Inv-TRSM, right-looking.
+//   X(S_i)      = Linv_ii * B'(S_i)                 (solve line)
+//   B'(T_{i+1}) = B'(T_{i+1}) - L(T_{i+1},S_i) X(S_i) (update lines)
+// B' lives in the workspace R; the first step reads B directly (or a copy of
+// B(S_0) when X is B).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+trsm_status sweep_right(const trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, const T* B,
+                        int64_t ldb, T* X, int64_t ldx, T* R, hipStream_t s) {
+  const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
+  const bool alias = (const void*)X == (const void*)B;
+  const T* src0 = B;
+  int64_t ld_src0 = ldb;
+  if (alias) {
+    TRSM_HIP(launch_copy2d<T, T>(B, ldb, R, k, std::min(n0, n), k, 1.0, s));
+    src0 = R;
+    ld_src0 = k;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
+    const T* src = (i == 0) ? src0 + r0 * ld_src0 : R + r0 * k;
+    const int64_t ld_src = (i == 0) ? ld_src0 : k;
+    TRSM_HIP(gemm_simple<T>(Linv + i * n0 * n0, n0, src, ld_src, nullptr, 0, X + r0 * ldx, ldx,
+                            sz, k, sz, 1.0, 0.0, G_A_LOWER, s));
+    if (i + 1 < m) {
+      const int64_t t0 = r0 + n0, rows = n - t0;
+      const T* cin = (i == 0) ? B + t0 * ldb : R + t0 * k;
+      const int64_t ldci = (i == 0) ? ldb : k;
+      TRSM_HIP(gemm_simple<T>(L + t0 * ldl + r0, ldl, X + r0 * ldx, ldx, cin, ldci, R + t0 * k, k,
+                              rows, k, sz, -1.0, 1.0, 0u, s));
+    }
+  }
+  return TRSM_OK;
+}
+
+// Recursive baseline (Alg. Rec-TRSM order on one GPU): X1 = solve(L11, B1);
+// B2 -= L21 X1; X2 = solve(L22, B2); substitution leaves, no inversion.
+template <typename T>
+trsm_status rec_solve(int64_t n, int64_t k, const T* L, int64_t ldl, T* X, int64_t ldx,
+                      int64_t leaf, hipStream_t s) {
+  if (n <= 0) return TRSM_OK;
+  if (n <= leaf) {
+    TRSM_HIP(launch_subst_leaf<T>(L, ldl, X, ldx, n, k, s));
+    return TRSM_OK;
+  }
+  int64_t n1 = ((n / 2 + leaf - 1) / leaf) * leaf;
+  if (n1 >= n) n1 = n - leaf;
+  TRSM_TRY(rec_solve<T>(n1, k, L, ldl, X, ldx, leaf, s));
+  TRSM_HIP(gemm_simple<T>(L + n1 * ldl, ldl, X, ldx, X + n1 * ldx, ldx, X + n1 * ldx, ldx, n - n1,
+                          k, n1, -1.0, 1.0, 0u, s));
+  return rec_solve<T>(n - n1, k, L + n1 * ldl + n1, ldl, X + n1 * ldx, ldx, leaf, s);
+}
+
+// ---------------------------------------------------------------------------
+// A4-A6: mixed precision.  Low-precision sweep (binary32 diagonal apply with
+// the binary32 copy of Linv, bfloat16/half trailing update with binary32
+// accumulation and per-(row, block) power-of-two scales), binary64 residual,
+// iterative refinement.
+// ---------------------------------------------------------------------------
+template <typename TL>
+trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
+                      const float* rscale, const double* rhs, int64_t ldr, double scale, float* Rl,
+                      float* D, TL* XlowT, hipStream_t s) {
+  const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
+  TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
+    // D(S_i) = Linv32_ii * Rl(S_i); also XlowT(:, S_i) = low(D(S_i))^T
+    {
+      auto p = gemm_params<float, float, float, TL>();
+      p.A = Linv32 + i * n0 * n0; p.lda = n0;
+      p.B = Rl + r0 * k; p.ldb = k;
+      p.Cout = D + r0 * k; p.ldco = k;
+      p.C2 = XlowT + r0; p.ldc2 = n;
+      p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
+      p.flags = G_A_LOWER | G_C2_T;
+      TRSM_HIP((launch_gemm<float, float, float, TL, 128, 128, 2, 2, false>(p, 1, s)));
+    }
+    if (i + 1 < m) {
+      const int64_t t0 = r0 + n0, rows = n - t0;
+      auto p = gemm_params<TL, float, float, float>();
+      p.A = Llow + t0 * n + r0; p.lda = n;
+      p.B = XlowT + r0; p.ldb = n;            // stored k x n: column c of X is a row
+      p.Cin = Rl + t0 * k; p.ldci = k;
+      p.Cout = Rl + t0 * k; p.ldco = k;
+      p.rscale = rscale + t0 * m + i; p.ld_rs = m;
+      p.M = (int)rows; p.N = (int)k; p.K = (int)sz;
+      p.alpha = -1.0; p.beta = 1.0;
+      p.flags = G_BETA | G_ROWSCALE;
+      TRSM_HIP((launch_gemm<TL, float, float, float, 128, 128, 2, 2, true>(p, 1, s)));
+    }
+  }
+  return TRSM_OK;
+}
+
+double pow2_scale_for(double maxabs) {
+  if (!(maxabs > 0.0) || !isfinite(maxabs)) return 1.0;
+  return ldexp(1.0, -ilogb(maxabs));
+}
+
+template <typename TL>
+trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, const char* lbuf,
+                        const double* B, int64_t ldb, double* X, int64_t ldx, char* ws,
+                        hipStream_t s, trsm_info* info) {
+  const int64_t n = P.n, k = P.k;
+  const float* Linv32 = (const float*)(lbuf + P.off_linv32);
+  const TL* Llow = (const TL*)(lbuf + P.off_llow);
+  const float* rscale = (const float*)(lbuf + P.off_rscale);
+  const double* d_lnorm = (const double*)(lbuf + P.off_lnorm);
+  double* R64 = (double*)(ws + P.ws_r64);
+  float* Rl = (float*)(ws + P.ws_rl);
+  float* D = (float*)(ws + P.ws_d);
+  TL* XlowT = (TL*)(ws + P.ws_xlow);
+  double* part = (double*)(ws + P.ws_part);
+  double* dnorm = (double*)(ws + P.ws_norm);
+
+  double h[4];
+  // ||L||_F (stored by trsm_invert_diag) and max |B| for the first scale.
+  TRSM_HIP(launch_sumsq_max(B, ldb, n, k, part, dnorm, s));
+  TRSM_HIP(hipMemcpyAsync(h, dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  double lnorm = 0.0;
+  TRSM_HIP(hipMemcpyAsync(&lnorm, d_lnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  TRSM_HIP(hipStreamSynchronize(s));
+  lnorm = sqrt(lnorm);
+  const bool alias = (const void*)X == (const void*)B;
+  const double u = ldexp(1.0, -53);
+
+  double scale = pow2_scale_for(h[1]);
+  TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, s));
+  TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, true, s));
+  if (info) {
+    info->iterations = 0;
+    info->converged = 0;
+    info->backward_error = -1.0;
+    info->correction = -1.0;
+    info->unrefined_error = -1.0;
+  }
+  if (P.flags & TRSM_FLAG_NO_REFINE) {
+    if (info) info->converged = 1;
+    return TRSM_OK;
+  }
+  if (alias) return TRSM_EINVAL;  // refinement needs the original B (checked earlier too)
+
+  double prev_corr = -1.0;
+  for (int it = 1; it <= 10; ++it) {
+    // R = B - L X (binary64) and its norms, ||X||
+    TRSM_HIP(gemm_simple<double>(L, ldl, X, ldx, B, ldb, R64, k, n, k, n, -1.0, 1.0, G_A_LOWER, s));
+    TRSM_HIP(launch_sumsq_max(R64, k, n, k, part, dnorm, s));
+    TRSM_HIP(launch_sumsq_max(X, ldx, n, k, part, dnorm + 2, s));
+    TRSM_HIP(hipMemcpyAsync(h, dnorm, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TRSM_HIP(hipStreamSynchronize(s));
+    const double rn = sqrt(h[0]), xn = sqrt(h[2]);
+    const double berr = (lnorm * xn > 0) ? rn / (lnorm * xn) : rn;
+    if (info) info->backward_error = berr;
+    if (berr <= 4.0 * u || rn == 0.0) {
+      if (info) info->converged = 1;
+      return TRSM_OK;
+    }
+    scale = pow2_scale_for(h[1]);
+    TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, R64, k, scale, Rl, D, XlowT, s));
+    TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, false, s));
+    // ||D|| (binary32 values, exact in binary64) for the stopping test
+    TRSM_HIP(launch_copy2d<float, double>(D, k, R64, k, n, k, 1.0 / scale, s));
+    TRSM_HIP(launch_sumsq_max(R64, k, n, k, part, dnorm, s));
+    TRSM_HIP(hipMemcpyAsync(h, dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TRSM_HIP(hipStreamSynchronize(s));
+    const double corr = (xn > 0) ? sqrt(h[0]) / xn : sqrt(h[0]);
+    if (info) {
+      info->iterations = it;
+      info->correction = corr;
+      if (it == 1) info->unrefined_error = corr;
+    }
+    // Stop when the correction is negligible, or when the observed
+    // contraction predicts that the next one would be.
+    bool done = corr <= 1e-13;
+    if (!done && prev_corr > 0) {
+      const double rho = corr / prev_corr;
+      done = rho <= 0.1 && corr * rho <= 1e-14;
+    }
+    prev_corr = corr;
+    if (done) {
+      if (info) info->converged = 1;
+      return TRSM_OK;
+    }
+  }
+  return TRSM_ENOTCONVERGED;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* trsm_status_string(trsm_status s) {
+  switch (s) {
+    case TRSM_OK: return "TRSM_OK";
+    case TRSM_EINVAL: return "TRSM_EINVAL";
+    case TRSM_ESINGULAR: return "TRSM_ESINGULAR";
+    case TRSM_ENOMEM: return "TRSM_ENOMEM";
+    case TRSM_EHIP: return "TRSM_EHIP";
+    case TRSM_ENOTCONVERGED: return "TRSM_ENOTCONVERGED";
+    case TRSM_EBUSY: return "TRSM_EBUSY";
+  }
+  return "TRSM_UNKNOWN";
+}
+
+int trsm_last_hip_error(void) { return g_last_hip; }
+
+trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uint32_t flags,
+                      trsm_plan_t* out) {
+  if (!out) return TRSM_EINVAL;
+  *out = nullptr;
+  if (n < 0 || k < 0 || n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return TRSM_EINVAL;
+  if (prec != TRSM_F64 && prec != TRSM_F32 && !is_mixed(prec)) return TRSM_EINVAL;
+  if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
+  if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
+  if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE)) return TRSM_EINVAL;
+  if (n * k > ((int64_t)1 << 31) - 1 || n * n > ((int64_t)1 << 31) * 8) return TRSM_EINVAL;
+  trsm_plan_s* P = new (std::nothrow) trsm_plan_s();
+  if (!P) return TRSM_ENOMEM;
+  P->n = n;
+  P->k = k;
+  P->prec = prec;
+  P->flags = flags;
+  P->n0_paper = paper_rule_n0(n, k);
+  if (n0 == 0) n0 = auto_n0(n, k, prec);
+  const int64_t cap = next_pow2(n < 1 ? 1 : n);
+  if (n0 > cap) n0 = cap;
+  P->n0 = n0;
+  P->m = n > 0 ? ceil_div(n, n0) : 0;
+  P->leaf = std::min<int64_t>(n0, 64);
+  const int64_t m = P->m;
+  // Linv buffer
+  size_t off = 0;
+  P->off_linv64 = off;
+  off = align_up(off + (size_t)m * n0 * n0 * 8);
+  if (prec != TRSM_F64) {
+    P->off_linv32 = off;
+    off = align_up(off + (size_t)m * n0 * n0 * 4);
+  }
+  if (is_mixed(prec)) {
+    P->off_llow = off;
+    off = align_up(off + (size_t)n * n * 2);
+    P->off_rscale = off;
+    off = align_up(off + (size_t)n * m * 4);
+    P->off_lnorm = off;
+    off = align_up(off + 8);
+    P->off_lpart = off;
+    off = align_up(off + 2 * kNormBlocks * 8 + 16);
+  }
+  P->linv_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : off;
+  // workspace
+  off = 0;
+  if (flags & TRSM_FLAG_RECURSIVE) {
+    // in place in X
+  } else if (!is_mixed(prec)) {
+    P->ws_r = off;
+    off = align_up(off + (size_t)n * k * elem_size(prec));
+  } else {
+    P->ws_r64 = off;
+    off = align_up(off + (size_t)n * k * 8);
+    P->ws_rl = off;
+    off = align_up(off + (size_t)n * k * 4);
+    P->ws_d = off;
+    off = align_up(off + (size_t)n * k * 4);
+    P->ws_xlow = off;
+    off = align_up(off + (size_t)n * k * 2);
+    P->ws_part = off;
+    off = align_up(off + 2 * kNormBlocks * 8);
+    P->ws_norm = off;
+    off = align_up(off + 8 * 8);
+  }
+  P->ws_bytes = off;
+  *out = P;
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_get_info(trsm_plan_t P, trsm_plan_info* info) {
+  if (!P || !info) return TRSM_EINVAL;
+  info->n = P->n;
+  info->k = P->k;
+  info->n0 = P->n0;
+  info->m = P->m;
+  info->leaf = P->leaf;
+  info->n0_paper_rule = P->n0_paper;
+  info->precision = (int32_t)P->prec;
+  info->flags = P->flags;
+  info->linv_bytes = P->linv_bytes;
+  info->workspace_bytes = P->ws_bytes;
+  info->inv_flops = (double)P->n * (double)P->n0 * (double)P->n0 / 3.0;
+  info->solve_flops = (double)P->n * (double)P->n * (double)P->k;
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_destroy(trsm_plan_t P) {
+  if (!P) return TRSM_OK;
+  if (P->d_bad) (void)hipFree(P->d_bad);
+  delete P;
+  return TRSM_OK;
+}
+
+trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Linv, void* stream) {
+  if (!P) return TRSM_EINVAL;
+  if (P->flags & TRSM_FLAG_RECURSIVE) return TRSM_OK;
+  if (P->n == 0) return TRSM_OK;
+  if (!L || !Linv || ldl < P->n) return TRSM_EINVAL;
+  if (((uintptr_t)Linv) % kAlign) return TRSM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)Linv;
+  double* L64 = (double*)(base + P->off_linv64);
+  const int64_t n = P->n, n0 = P->n0, m = P->m;
+  if (!P->d_bad) {
+    // the status word is made on first use, on the current device
+    if (hipMalloc((void**)&P->d_bad, sizeof(unsigned long long)) != hipSuccess) {
+      P->d_bad = nullptr;
+      return TRSM_ENOMEM;
+    }
+  }
+  TRSM_HIP(hipMemsetAsync(P->d_bad, 0xFF, sizeof(unsigned long long), s));
+  if (P->prec == TRSM_F32)
+    TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s));
+  else
+    TRSM_HIP(launch_extract_diag<double>((const double*)L, ldl, n, n0, m, L64, P->d_bad, s));
+  TRSM_HIP(launch_trtri_leaf(L64, n0, m, P->leaf, s));
+  if (P->leaf < n0) {
+    TRSM_HIP(rec_tri_inv_levels(L64, n0, m, P->leaf, s));
+    TRSM_HIP(launch_zero_upper(L64, n0, m, s));
+  }
+  if (P->prec != TRSM_F64)
+    TRSM_HIP((launch_convert<double, float>(L64, (float*)(base + P->off_linv32), m * n0 * n0, s)));
+  if (is_mixed(P->prec)) {
+    float* rs = (float*)(base + P->off_rscale);
+    if (P->prec == TRSM_MIXED_BF16)
+      TRSM_HIP(launch_lowcopy<bf16_t>((const double*)L, ldl, n, n0, m, (bf16_t*)(base + P->off_llow),
+                                      rs, 1.0f, s));
+    else
+      TRSM_HIP(launch_lowcopy<f16_t>((const double*)L, ldl, n, n0, m, (f16_t*)(base + P->off_llow),
+                                     rs, 16384.0f, s));
+    // ||L||_F^2 over the lower triangle, kept for the backward-error test
+    double* part = (double*)(base + P->off_lpart);
+    double* res = part + 2 * kNormBlocks;
+    TRSM_HIP(launch_sumsq_lower<double>((const double*)L, ldl, n, part, res, s));
+    TRSM_HIP((launch_copy2d<double, double>(res, 1, (double*)(base + P->off_lnorm), 1, 1, 1, 1.0, s)));
+  }
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_last_error(trsm_plan_t P, trsm_status* status, int64_t* index) {
+  if (!P || !status || !index) return TRSM_EINVAL;
+  unsigned long long v = ~0ull;
+  if (P->d_bad) TRSM_HIP(hipMemcpy(&v, P->d_bad, sizeof(v), hipMemcpyDeviceToHost));
+  if (v == ~0ull) {
+    *status = TRSM_OK;
+    *index = -1;
+  } else {
+    *status = TRSM_ESINGULAR;
+    *index = (int64_t)v;
+  }
+  return TRSM_OK;
+}
+
+trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv, const void* B,
+                       int64_t ldb, void* X, int64_t ldx, void* workspace, void* stream,
+                       trsm_info* info) {
+  if (!P) return TRSM_EINVAL;
+  if (info) {
+    info->iterations = 0;
+    info->converged = 1;
+    info->backward_error = -1.0;
+    info->correction = -1.0;
+    info->unrefined_error = -1.0;
+  }
+  const int64_t n = P->n, k = P->k;
+  if (n == 0 || k == 0) return TRSM_OK;
+  const bool rec = P->flags & TRSM_FLAG_RECURSIVE;
+  if (!L || !B || !X || (!rec && !Linv)) return TRSM_EINVAL;
+  if (ldl < n || ldb < k || ldx < k) return TRSM_EINVAL;
+  if (P->ws_bytes && !workspace) return TRSM_EINVAL;
+  if (workspace && ((uintptr_t)workspace) % kAlign) return TRSM_EINVAL;
+  if (Linv && ((uintptr_t)Linv) % kAlign) return TRSM_EINVAL;
+  const size_t es = elem_size(P->prec);
+  const size_t bbytes = ((size_t)(n - 1) * ldb + k) * es, xbytes = ((size_t)(n - 1) * ldx + k) * es;
+  if (ranges_overlap(B, bbytes, X, xbytes) && !(B == X && ldb == ldx)) return TRSM_EINVAL;
+  if (is_mixed(P->prec) && B == X && !(P->flags & TRSM_FLAG_NO_REFINE)) return TRSM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const char* lb = (const char*)Linv;
+  char* ws = (char*)workspace;
+  if (rec) {
+    if (P->prec == TRSM_F64) {
+      if (X != B) TRSM_HIP(launch_copy2d<double, double>((const double*)B, ldb, (double*)X, ldx, n, k, 1.0, s));
+      return rec_solve<double>(n, k, (const double*)L, ldl, (double*)X, ldx, 64, s);
+    }
+    if (X != B) TRSM_HIP(launch_copy2d<float, float>((const float*)B, ldb, (float*)X, ldx, n, k, 1.0, s));
+    return rec_solve<float>(n, k, (const float*)L, ldl, (float*)X, ldx, 64, s);
+  }
+  switch (P->prec) {
+    case TRSM_F64:
+      return sweep_right<double>(*P, (const double*)L, ldl, (const double*)(lb + P->off_linv64),
+                                 (const double*)B, ldb, (double*)X, ldx, (double*)(ws + P->ws_r), s);
+    case TRSM_F32:
+      return sweep_right<float>(*P, (const float*)L, ldl, (const float*)(lb + P->off_linv32),
+                                (const float*)B, ldb, (float*)X, ldx, (float*)(ws + P->ws_r), s);
+    case TRSM_MIXED_BF16:
+      return solve_mixed<bf16_t>(*P, (const double*)L, ldl, lb, (const double*)B, ldb, (double*)X,
+                                 ldx, ws, s, info);
+    case TRSM_MIXED_F16:
+      return solve_mixed<f16_t>(*P, (const double*)L, ldl, lb, (const double*)B, ldb, (double*)X,
+                                ldx, ws, s, info);
+  }
+  return TRSM_EINVAL;
+}
+
+size_t trsm_residual_workspace_bytes(int64_t n, int64_t k) {
+  (void)n;
+  (void)k;
+  return align_up(2 * kNormBlocks * 8) + align_up(8 * 8);
+}
+
+trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl, const double* X,
+                          int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
+                          void* workspace, double* norms, void* stream) {
+  if (n < 0 || k < 0 || !norms) return TRSM_EINVAL;
+  norms[0] = norms[1] = norms[2] = 0.0;
+  if (n == 0 || k == 0) return TRSM_OK;
+  if (!L || !X || !B || !R || !workspace) return TRSM_EINVAL;
+  if (ldl < n || ldx < k || ldb < k || ldr < k) return TRSM_EINVAL;
+  const size_t rb = ((size_t)(n - 1) * ldr + k) * 8;
+  if (ranges_overlap(R, rb, X, ((size_t)(n - 1) * ldx + k) * 8) ||
+      ranges_overlap(R, rb, B, ((size_t)(n - 1) * ldb + k) * 8) ||
+      ranges_overlap(R, rb, L, ((size_t)(n - 1) * ldl + n) * 8))
+    return TRSM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double* part = (double*)workspace;
+  double* dn = (double*)((char*)workspace + align_up(2 * kNormBlocks * 8));
+  TRSM_HIP(gemm_simple<double>(L, ldl, X, ldx, B, ldb, R, ldr, n, k, n, -1.0, 1.0, G_A_LOWER, s));
+  TRSM_HIP(launch_sumsq_max(R, ldr, n, k, part, dn, s));
+  TRSM_HIP(launch_sumsq_max(X, ldx, n, k, part, dn + 2, s));
+  double h[4];
+  TRSM_HIP(hipMemcpyAsync(h, dn, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  TRSM_HIP(hipStreamSynchronize(s));
+  norms[0] = sqrt(h[0]);
+  norms[1] = sqrt(h[2]);
+  norms[2] = h[1];
+  return TRSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of ``include/trsm.h`` (argument marshalling only).
+
+Every function with a ``trsm_`` name forwards to the C entry point of the
+same name in ``libtrsm.so``; all arithmetic happens in the library's HIP
+kernels.  PyTorch is used only to own device memory and to name the stream:
+tensors are passed as raw device pointers (``data_ptr()``) with their row
+strides as leading dimensions.
+
+The library must have been built (``python -m paper_1612_01855_amd.build``);
+importing this module without it raises ``RuntimeError`` -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrsm.so")
+
+# trsm_status
+OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENOTCONVERGED, EBUSY = range(7)
+# trsm_precision
+F64, F32, MIXED_BF16, MIXED_F16 = range(4)
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16}
+# plan flags
+FLAG_NO_REFINE = 0x1
+FLAG_RECURSIVE = 0x2
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int64), ("n0", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("leaf", ctypes.c_int64),
+                ("n0_paper_rule", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("linv_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("inv_flops", ctypes.c_double),
+                ("solve_flops", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("backward_error", ctypes.c_double), ("correction", ctypes.c_double),
+                ("unrefined_error", ctypes.c_double)]
+
+
+EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
+           "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
+           "trsm_residual_workspace_bytes", "trsm_residual"]
+
+
+class TrsmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}"
+                         + (f" (hip error {_lib.trsm_last_hip_error()})" if status == EHIP else ""))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1612_01855_amd.build` (no fallback path exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, u32, vp, i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    lib.trsm_status_string.argtypes = [i32]
+    lib.trsm_status_string.restype = ctypes.c_char_p
+    lib.trsm_last_hip_error.argtypes = []
+    lib.trsm_last_hip_error.restype = i32
+    lib.trsm_plan.argtypes = [i64, i64, i32, i64, u32, ctypes.POINTER(vp)]
+    lib.trsm_plan.restype = i32
+    lib.trsm_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.trsm_plan_get_info.restype = i32
+    lib.trsm_plan_destroy.argtypes = [vp]
+    lib.trsm_plan_destroy.restype = i32
+    lib.trsm_invert_diag.argtypes = [vp, vp, i64, vp, vp]
+    lib.trsm_invert_diag.restype = i32
+    lib.trsm_plan_last_error.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.trsm_plan_last_error.restype = i32
+    lib.trsm_solve.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(Info)]
+    lib.trsm_solve.restype = i32
+    lib.trsm_residual_workspace_bytes.argtypes = [i64, i64]
+    lib.trsm_residual_workspace_bytes.restype = ctypes.c_size_t
+    lib.trsm_residual.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                  ctypes.POINTER(ctypes.c_double), vp]
+    lib.trsm_residual.restype = i32
+    return lib
+
+
+_lib = _load()
+
+
+def status_string(status: int) -> str:
+    return _lib.trsm_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise TrsmError(status, where)
+
+
+# ---- raw entry points (same names as the C ABI) ------------------------------
+
+def trsm_plan(n: int, k: int, precision: int = F64, n0: int = 0, flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.trsm_plan(n, k, precision, n0, flags, ctypes.byref(h)), "trsm_plan")
+    return h.value
+
+
+def trsm_plan_get_info(plan: int) -> PlanInfo:
+    info = PlanInfo()
+    _check(_lib.trsm_plan_get_info(plan, ctypes.byref(info)), "trsm_plan_get_info")
+    return info
+
+
+def trsm_plan_destroy(plan: int) -> None:
+    _check(_lib.trsm_plan_destroy(plan), "trsm_plan_destroy")
+
+
+def trsm_invert_diag(plan: int, L: int, ldl: int, Linv: int, stream: int = 0) -> None:
+    _check(_lib.trsm_invert_diag(plan, L, ldl, Linv, stream), "trsm_invert_diag")
+
+
+def trsm_plan_last_error(plan: int):
+    st, idx = ctypes.c_int(), ctypes.c_int64()
+    _check(_lib.trsm_plan_last_error(plan, ctypes.byref(st), ctypes.byref(idx)),
+           "trsm_plan_last_error")
+    return st.value, idx.value
+
+
+def trsm_solve(plan: int, L: int, ldl: int, Linv: int, B: int, ldb: int, X: int, ldx: int,
+               workspace: int, stream: int = 0, info: Optional[Info] = None) -> int:
+    """Returns the raw status (TRSM_ENOTCONVERGED is not raised)."""
+    st = _lib.trsm_solve(plan, L, ldl, Linv, B, ldb, X, ldx, workspace, stream,
+                         ctypes.byref(info) if info is not None else None)
+    if st not in (OK, ENOTCONVERGED):
+        raise TrsmError(st, "trsm_solve")
+    return st
+
+
+def trsm_residual_workspace_bytes(n: int, k: int) -> int:
+    return int(_lib.trsm_residual_workspace_bytes(n, k))
+
+
+def trsm_residual(n: int, k: int, L: int, ldl: int, X: int, ldx: int, B: int, ldb: int,
+                  R: int, ldr: int, workspace: int, stream: int = 0):
+    norms = (ctypes.c_double * 3)()
+    _check(_lib.trsm_residual(n, k, L, ldl, X, ldx, B, ldb, R, ldr, workspace, norms, stream),
+           "trsm_residual")
+    return tuple(norms)
+
+
+# ---- torch-tensor convenience (memory ownership only) ------------------------
+
+def _stream_handle(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ld(t) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D with unit column stride (row-major)")
+    return max(t.stride(0), t.shape[1], 1)
+
+
+@dataclass
+class Solver:
+    """Owns a plan plus the Linv and workspace buffers (torch uint8 tensors)."""
+    plan: int
+    info: PlanInfo
+    linv: object
+    workspace: object
+
+    @classmethod
+    def create(cls, n: int, k: int, precision: str = "f64", n0: int = 0, flags: int = 0,
+               device: str = "cuda"):
+        import torch
+        plan = trsm_plan(n, k, PRECISIONS[precision], n0, flags)
+        info = trsm_plan_get_info(plan)
+        linv = torch.empty(max(info.linv_bytes, 1) + 256, dtype=torch.uint8, device=device)
+        ws = torch.empty(max(info.workspace_bytes, 1) + 256, dtype=torch.uint8, device=device)
+        return cls(plan, info, linv, ws)
+
+    @staticmethod
+    def _aligned(buf) -> int:
+        p = buf.data_ptr()
+        return (p + 255) // 256 * 256
+
+    @property
+    def linv_ptr(self) -> int:
+        return self._aligned(self.linv)
+
+    @property
+    def workspace_ptr(self) -> int:
+        return self._aligned(self.workspace)
+
+    def invert(self, L) -> None:
+        import torch
+        trsm_invert_diag(self.plan, L.data_ptr(), _ld(L), self.linv_ptr,
+                         _stream_handle(torch, L.device))
+
+    def solve(self, L, B, X=None, info: Optional[Info] = None) -> object:
+        import torch
+        if X is None:
+            X = torch.empty_like(B)
+        trsm_solve(self.plan, L.data_ptr(), _ld(L), self.linv_ptr, B.data_ptr(), _ld(B),
+                   X.data_ptr(), _ld(X), self.workspace_ptr, _stream_handle(torch, B.device),
+                   info)
+        return X
+
+    def last_error(self):
+        return trsm_plan_last_error(self.plan)
+
+    def close(self):
+        if self.plan:
+            trsm_plan_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None):
+    """X = L^{-1} B on the GPU: plan, invert the diagonal blocks, sweep."""
+    n, k = B.shape
+    s = Solver.create(n, k, precision, n0, flags, device=B.device)
+    try:
+        if not (flags & FLAG_RECURSIVE):
+            s.invert(L)
+        return s.solve(L, B, info=info)
+    finally:
+        import torch
+        torch.cuda.current_stream(B.device).synchronize()
+        s.close()

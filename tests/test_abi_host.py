@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/trsm.h declares, validates arguments, and plans the
+blocking (Sec. VIII rule reported, n0 power of two, buffer sizes)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trsm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1612_01855_amd import trsm
+    return trsm
+
+
+def test_header_declares_the_named_calls():
+    names = declared_functions()
+    for required in ["trsm_plan", "trsm_invert_diag", "trsm_solve"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(T):
+    lib = ctypes.CDLL(T.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+    assert set(T.EXPORTS) <= set(declared_functions())
+
+
+def test_status_strings(T):
+    assert T.status_string(T.OK) == "TRSM_OK"
+    assert T.status_string(T.ESINGULAR) == "TRSM_ESINGULAR"
+    assert T.status_string(99) == "TRSM_UNKNOWN"
+
+
+@pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
+                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80),
+                                  (8, 8, 2, 0, 2)])
+def test_plan_rejects_bad_arguments(T, args):
+    with pytest.raises(T.TrsmError) as e:
+        T.trsm_plan(*args)
+    assert e.value.status == T.EINVAL
+
+
+def test_plan_null_out_pointer(T):
+    lib = T._lib
+    assert lib.trsm_plan(4, 4, 0, 0, 0, None) == T.EINVAL
+    assert lib.trsm_plan_get_info(None, None) == T.EINVAL
+    assert lib.trsm_plan_destroy(None) == T.OK
+
+
+@pytest.mark.parametrize("n,k,expect", [(16384, 16384, 16384), (16384, 128, 431),
+                                        (16384, 2048, 3444), (16384, 32768, 16384),
+                                        (256, 64, 128), (4096, 1024, 2048)])
+def test_paper_rule_reported(T, n, k, expect):
+    # Sec. VIII at p = 1: n < 4k -> n0 = n; n > 4k -> (n k^3)^(1/4); n = 4k -> min(sqrt(nk), n)
+    p = T.trsm_plan(n, k, T.F64, 0, 0)
+    try:
+        assert T.trsm_plan_get_info(p).n0_paper_rule == expect
+    finally:
+        T.trsm_plan_destroy(p)
+
+
+@pytest.mark.parametrize("n,k,n0", [(256, 64, 32), (1000, 7, 0), (1, 1, 0), (0, 5, 0),
+                                    (7, 0, 4), (300, 20, 1024), (8192, 8192, 0)])
+def test_plan_layout(T, n, k, n0):
+    p = T.trsm_plan(n, k, T.F64, n0, 0)
+    try:
+        i = T.trsm_plan_get_info(p)
+        assert i.n0 >= 1 and (i.n0 & (i.n0 - 1)) == 0
+        if n0:
+            assert i.n0 == min(n0, 1 << max(n - 1, 0).bit_length())
+        assert i.m == (-(-n // i.n0) if n else 0)
+        assert i.leaf == min(i.n0, 64)
+        assert i.linv_bytes >= i.m * i.n0 * i.n0 * 8
+        assert i.workspace_bytes >= n * k * 8
+        assert i.solve_flops == float(n) * n * k
+    finally:
+        T.trsm_plan_destroy(p)
+
+
+def test_mixed_plan_has_low_precision_copies(T):
+    p64 = T.trsm_plan(512, 64, T.F64, 128, 0)
+    pb = T.trsm_plan(512, 64, T.MIXED_BF16, 128, 0)
+    try:
+        a, b = T.trsm_plan_get_info(p64), T.trsm_plan_get_info(pb)
+        assert b.linv_bytes >= a.linv_bytes + 4 * 512 * 128 + 2 * 512 * 512
+        assert b.workspace_bytes > a.workspace_bytes
+    finally:
+        T.trsm_plan_destroy(p64)
+        T.trsm_plan_destroy(pb)
+
+
+def test_solve_argument_validation_without_gpu(T):
+    p = T.trsm_plan(64, 8, T.F64, 16, 0)
+    try:
+        lib = T._lib
+        fake = 1 << 20      # never dereferenced: validation fails first
+        # null L
+        assert lib.trsm_solve(p, None, 64, fake, fake, 8, fake + 4096, 8, fake, None, None) == T.EINVAL
+        # ldl < n
+        assert lib.trsm_solve(p, fake, 63, fake, fake, 8, fake + 4096, 8, fake, None, None) == T.EINVAL
+        # ldb < k
+        assert lib.trsm_solve(p, fake, 64, fake, fake, 7, fake + 4096, 8, fake, None, None) == T.EINVAL
+        # partial overlap of B and X
+        assert lib.trsm_solve(p, fake, 64, fake, fake, 8, fake + 8, 8, fake, None, None) == T.EINVAL
+        # misaligned workspace
+        assert lib.trsm_solve(p, fake, 64, fake, fake, 8, fake + 65536, 8, fake + 8, None, None) == T.EINVAL
+        # null Linv / L for invert
+        assert lib.trsm_invert_diag(p, None, 64, fake, None) == T.EINVAL
+        assert lib.trsm_invert_diag(p, fake, 10, fake, None) == T.EINVAL
+    finally:
+        T.trsm_plan_destroy(p)
+
+
+def test_residual_validation_without_gpu(T):
+    lib = T._lib
+    norms = (ctypes.c_double * 3)()
+    fake = 1 << 20
+    assert lib.trsm_residual(4, 4, fake, 4, fake + 4096, 4, fake + 8192, 4, fake + 8192, 4,
+                             fake, norms, None) == T.EINVAL   # R overlaps B
+    assert lib.trsm_residual(4, 4, fake, 3, fake + 4096, 4, fake + 8192, 4, fake + 16384, 4,
+                             fake, norms, None) == T.EINVAL   # ldl < n
+    assert lib.trsm_residual(0, 4, None, 0, None, 4, None, 4, None, 4, None, norms, None) == T.OK

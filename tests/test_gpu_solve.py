@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Tolerances (relative Frobenius error against the oracle):
+1e-12 for binary64 and for refined mixed precision, 1e-5 for binary32 (the
+oracle then runs on the binary32-rounded inputs)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_01855_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1612_01855_amd import trsm
+    return trsm
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def gpu_solve(torch, T, L, B, precision="f64", n0=0, flags=0, info=None):
+    dt = torch.float32 if precision == "f32" else torch.float64
+    Ld, Bd = dev(torch, L, dt), dev(torch, B, dt)
+    X = T.solve(Ld, Bd, precision=precision, n0=n0, flags=flags, info=info)
+    torch.cuda.synchronize()
+    return host(X)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+# ---- binary64 sweep -----------------------------------------------------------
+
+def test_config0_n256_k64_n0_32(torch, T):
+    L, B = gen.easy_system(256, 64, 0, upper=np.nan)
+    X = gpu_solve(torch, T, L, B, n0=32)
+    err = oracle.rel_fro_err(X, oracle.trsm(L, B))
+    log(f"config0 f64 rel err {err:.3e}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("n,k,n0", [(1, 1, 0), (7, 3, 4), (33, 5, 16), (33, 5, 64),
+                                    (1000, 1, 0), (1000, 64, 128), (200, 129, 32),
+                                    (513, 77, 256), (130, 300, 1), (64, 64, 2)])
+def test_ragged_shapes(torch, T, n, k, n0):
+    L, B = gen.easy_system(n, k, n + k, upper=np.nan)
+    X = gpu_solve(torch, T, L, B, n0=n0)
+    err = oracle.rel_fro_err(X, oracle.trsm(L, B))
+    log(f"n={n} k={k} n0={n0} rel err {err:.3e}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("n0", [16, 32, 64, 128, 256, 512, 1024])
+def test_n0_invariance(torch, T, n0):
+    # n0 = n is the full inversion approach; small n0 the usual blocked TRSM.
+    L, B = gen.easy_system(700, 96, 3, upper=np.nan)
+    X = gpu_solve(torch, T, L, B, n0=n0)
+    assert oracle.rel_fro_err(X, oracle.trsm(L, B)) <= TOL64
+
+
+def test_integer_system_is_exact(torch, T):
+    n, k = 300, 40
+    L = gen.int_unit_lower(n, 5, density=0.02)
+    Xtrue = gen.int_rhs(n, k, 5, -2, 2)
+    B = L @ Xtrue
+    Linv_q = oracle.inv_lower(L)
+    assert np.abs(Linv_q).max() < 2 ** 40 and np.abs(B).max() < 2 ** 40
+    for n0 in (64, 256):
+        X = gpu_solve(torch, T, L, B, n0=n0)
+        assert np.array_equal(X, Xtrue), n0
+
+
+@pytest.mark.parametrize("n0", [64, 256, 512])
+def test_block_inverses_match_oracle(torch, T, n0):
+    n = 1000
+    L = gen.easy_lower(n, 9, upper=np.nan)
+    s = T.Solver.create(n, 4, "f64", n0)
+    try:
+        s.invert(dev(torch, L))
+        torch.cuda.synchronize()
+        m, n0e = s.info.m, s.info.n0
+        blocks = host(s.linv[(s.linv_ptr - s.linv.data_ptr()):][:m * n0e * n0e * 8]
+                      .view(torch.float64)).reshape(m, n0e, n0e)
+        ref = oracle.diag_block_inverses(L, n0e)
+        for b in range(m):
+            r = ref[b]
+            sz = r.shape[0]
+            got = blocks[b]
+            assert np.all(np.triu(got, 1) == 0)
+            assert np.abs(got[:sz, :sz] - r).max() <= 1e-13 * max(1.0, np.abs(r).max())
+            if sz < n0e:  # identity padding of the ragged block
+                assert np.array_equal(got[sz:, sz:], np.eye(n0e - sz))
+                assert np.all(got[sz:, :sz] == 0)
+    finally:
+        s.close()
+
+
+def test_integer_block_inverse_bitwise(torch, T):
+    n = 256
+    L = gen.int_unit_lower(n, 2, density=0.05)
+    ref = oracle.diag_block_inverses(L, 256)[0]
+    assert np.abs(ref).max() < 2 ** 50
+    s = T.Solver.create(n, 1, "f64", 256)
+    try:
+        s.invert(dev(torch, L))
+        torch.cuda.synchronize()
+        off = s.linv_ptr - s.linv.data_ptr()
+        got = host(s.linv[off:off + n * n * 8].view(torch.float64)).reshape(n, n)
+        assert np.array_equal(got, ref)
+    finally:
+        s.close()
+
+
+def test_in_place_and_leading_dimensions(torch, T):
+    n, k = 400, 50
+    L, B = gen.easy_system(n, k, 21, upper=np.nan)
+    Xref = oracle.trsm(L, B)
+    Lbig = np.full((n, n + 9), np.nan)
+    Lbig[:, :n] = L
+    Bbig = np.zeros((n, k + 6))
+    Bbig[:, :k] = B
+    Ld = dev(torch, Lbig)[:, :n]
+    Bd = dev(torch, Bbig)[:, :k]
+    s = T.Solver.create(n, k, "f64", 64)
+    try:
+        s.invert(Ld)
+        Xd = torch.zeros((n, k + 3), dtype=torch.float64, device="cuda")[:, :k]
+        s.solve(Ld, Bd, Xd)
+        torch.cuda.synchronize()
+        assert oracle.rel_fro_err(host(Xd), Xref) <= TOL64
+        s.solve(Ld, Bd, Bd)          # in place: X is B
+        torch.cuda.synchronize()
+        assert oracle.rel_fro_err(host(Bd), Xref) <= TOL64
+    finally:
+        s.close()
+
+
+def test_singular_diagonal_reported(torch, T):
+    n = 200
+    L = gen.easy_lower(n, 1)
+    L[137, 137] = 0.0
+    L[150, 150] = np.nan
+    s = T.Solver.create(n, 3, "f64", 64)
+    try:
+        s.invert(dev(torch, L))
+        torch.cuda.synchronize()
+        assert s.last_error() == (T.ESINGULAR, 137)
+        s.invert(dev(torch, gen.easy_lower(n, 2)))
+        torch.cuda.synchronize()
+        assert s.last_error() == (T.OK, -1)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("n,k", [(1024, 128), (512, 300)])
+def test_cholesky_family_f64(torch, T, n, k):
+    L = gen.chol_lower(n, 4, upper=np.nan)
+    B = gen.rhs(n, k, 4)
+    X = gpu_solve(torch, T, L, B)
+    assert oracle.rel_fro_err(X, oracle.trsm(L, B)) <= TOL64
+
+
+def test_hard_matrix_backward_stable(torch, T):
+    n, k = 1024, 16
+    L = gen.hard_lower(n, 2)
+    B = gen.rhs(n, k, 2)
+    X = gpu_solve(torch, T, L, B)
+    berr = oracle.backward_err(L, X, B)
+    fwd = oracle.rel_fro_err(X, oracle.trsm_q(L, B))
+    fwd_or = oracle.rel_fro_err(oracle.trsm(L, B), oracle.trsm_q(L, B))
+    log(f"hard L: backward {berr:.2e}, forward vs binary128 {fwd:.2e} (oracle's own {fwd_or:.2e})")
+    assert berr <= 1e-14
+    assert fwd <= 1e-7
+
+
+# ---- binary32 sweep -----------------------------------------------------------
+
+@pytest.mark.parametrize("n,k,n0", [(256, 64, 32), (1000, 33, 0), (777, 130, 128)])
+def test_f32_against_oracle_on_rounded_inputs(torch, T, n, k, n0):
+    L, B = gen.easy_system(n, k, 31, upper=np.nan)
+    L32 = L.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    X = gpu_solve(torch, T, L, B, precision="f32", n0=n0)
+    err = oracle.rel_fro_err(X, oracle.trsm(L32, B32))
+    log(f"f32 n={n} k={k} rel err {err:.2e}")
+    assert err <= TOL32
+
+
+def test_f32_cholesky_family(torch, T):
+    n, k = 1024, 256
+    L = gen.chol_lower(n, 6, upper=np.nan)
+    B = gen.rhs(n, k, 6)
+    L32 = L.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    X = gpu_solve(torch, T, L, B, precision="f32")
+    assert oracle.rel_fro_err(X, oracle.trsm(L32, B32)) <= TOL32
+
+
+# ---- recursive baseline -------------------------------------------------------
+
+@pytest.mark.parametrize("prec,n,k", [("f64", 1000, 70), ("f64", 64, 3), ("f32", 513, 40)])
+def test_recursive_baseline(torch, T, prec, n, k):
+    L, B = gen.easy_system(n, k, 41, upper=np.nan)
+    if prec == "f32":
+        Lr, Br = L.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+        tol = TOL32
+    else:
+        Lr, Br, tol = L, B, TOL64
+    X = gpu_solve(torch, T, L, B, precision=prec, flags=T.FLAG_RECURSIVE)
+    assert oracle.rel_fro_err(X, oracle.trsm(Lr, Br)) <= tol
+
+
+# ---- mixed precision with refinement ----------------------------------------------
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("n,k,n0", [(512, 64, 128), (1000, 40, 0)])
+def test_mixed_refined(torch, T, prec, n, k, n0):
+    L, B = gen.easy_system(n, k, 51, upper=np.nan)
+    info = T.Info()
+    X = gpu_solve(torch, T, L, B, precision=prec, n0=n0, info=info)
+    Xref = oracle.trsm(L, B)
+    err = oracle.rel_fro_err(X, Xref)
+    X0 = gpu_solve(torch, T, L, B, precision=prec, n0=n0, flags=T.FLAG_NO_REFINE)
+    err0 = oracle.rel_fro_err(X0, Xref)
+    log(f"{prec} n={n} k={k}: refined {err:.2e} after {info.iterations} corrections "
+        f"(berr {info.backward_error:.1e}); unrefined {err0:.2e}")
+    assert info.converged == 1
+    assert err <= TOL64
+    assert err0 <= 1e-2
+
+
+def test_mixed_hard_matrix(torch, T):
+    n, k = 512, 8
+    L = gen.hard_lower(n, 3)
+    B = gen.rhs(n, k, 3)
+    info = T.Info()
+    X = gpu_solve(torch, T, L, B, precision="bf16", info=info)
+    berr = oracle.backward_err(L, X, B)
+    log(f"mixed bf16 hard L: {info.iterations} corrections, converged={info.converged}, "
+        f"backward {berr:.2e}, forward vs binary128 {oracle.rel_fro_err(X, oracle.trsm_q(L, B)):.2e}")
+    if info.converged:
+        assert berr <= 1e-14
+
+
+# ---- residual entry point -----------------------------------------------------
+
+def test_residual_entry_point(torch, T):
+    n, k = 700, 30
+    L, B = gen.easy_system(n, k, 61, upper=np.nan)
+    X = oracle.trsm(L, B) + 1e-6 * gen.rhs(n, k, 62)
+    Ld, Xd, Bd = dev(torch, L), dev(torch, X), dev(torch, B)
+    Rd = torch.empty_like(Bd)
+    ws = torch.empty(T.trsm_residual_workspace_bytes(n, k), dtype=torch.uint8, device="cuda")
+    norms = T.trsm_residual(n, k, Ld.data_ptr(), n, Xd.data_ptr(), k, Bd.data_ptr(), k,
+                            Rd.data_ptr(), k, ws.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    Rref = oracle.residual(L, X, B)
+    scale = oracle.fro_lower(L) * oracle.fro(X)
+    assert oracle.fro(host(Rd) - Rref) <= 1e-15 * scale
+    assert abs(norms[0] - oracle.fro(Rref)) <= 1e-15 * scale
+    assert abs(norms[1] - oracle.fro(X)) <= 1e-14 * oracle.fro(X)
+    assert abs(norms[2] - np.abs(Rref).max()) <= 1e-15 * scale
