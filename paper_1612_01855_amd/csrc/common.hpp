@@ -20,10 +20,13 @@ constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------
 // Matrix-core traits.  Every 16x16 output tile is produced by the 16x16xK
-// MFMA of the element type; lane l of a wave holds output rows
-// 4*(l/16) + r (r = 0..3) of column l%16.  The reduction index a lane feeds
-// is picked by the kernel (any permutation of k, used consistently for both
-// operands, gives the same sum up to rounding order).
+// MFMA of the element type.  Operands: lane l feeds row l%16 of A and
+// column l%16 of B with kPerLane reduction indices; which k a lane feeds is
+// picked by the kernel (any permutation of k, used consistently for both
+// operands, gives the same sum up to rounding order).  Results: lane l holds
+// column l%16, and its four values r = 0..3 are rows out_row(l/16, r) --
+// 4*(l/16) + r for the binary32-accumulating instructions, 4*r + l/16 for the
+// binary64 one (checked on gfx950 against a host product).
 // ---------------------------------------------------------------------------
 template <typename T> struct Mfma;
 
@@ -35,6 +38,7 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int g, int r) { return 4 * r + g; }
 };
 
 template <> struct Mfma<float> {
@@ -45,6 +49,7 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
 };
 
 template <> struct Mfma<bf16_t> {
@@ -55,6 +60,7 @@ template <> struct Mfma<bf16_t> {
   static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
 };
 
 template <> struct Mfma<f16_t> {
@@ -65,6 +71,7 @@ template <> struct Mfma<f16_t> {
   static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
 };
 
 template <typename To, typename From>

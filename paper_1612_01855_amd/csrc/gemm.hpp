@@ -280,7 +280,7 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = r0 + wm * WTM + i * 16 + g * 4 + r;
+      const int row = r0 + wm * WTM + i * 16 + MF::out_row(g, r);
       if (row >= M) continue;
       Acc rs = Acc(1);
       if (use_rs) rs = static_cast<Acc>(p.rscale[(int64_t)row * p.ld_rs]);
