@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the inversion-based triangular solve on one MI355X.
+
+One step = one pass of the hot path over the workload: invert the n0 x n0
+diagonal blocks of L (Alg. Diagonal-Inverter / Alg. RecTriInv) and run the
+blocked sweep (Alg. It-Inv-TRSM) for all k right-hand sides, in binary64.
+Default workload: n = k = 16384, L with diagonal U[1,2] and strict lower
+U[-1,1]/n, B ~ N(0,1), seed 0.  The metric credits n^2 k flops per step.
+
+Prints ONE JSON line.  Also reported in that line:
+  roofline      -- the matrix-core GEMM kernel (every product launch of a step),
+                   timed live with hipEvents on the solve stream;
+  cpu_baseline  -- the CPU oracle (plain forward substitution) on a column
+                   sample of the same workload;
+  mixed         -- refined bfloat16 / half solves of the same system,
+                   compared with the binary64 solve;
+  check         -- backward error of the benchmarked X (binary64 residual).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("TRSM TFLOP/s (n²k) at n=k=16384; served p50/p99 latency; "
+          "mixed vs plain FP64")
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # TFLOP/s, dense
+KERNEL_SRC = os.path.join(ROOT, "paper_1612_01855_amd", "csrc", "gemm.hpp")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_gemm_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_sha") != kernel_hash():
+            return None
+        return float(d["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(L, B, seconds_hint: float = 15.0):
+    """Time the oracle on the first columns of the same B (column sample)."""
+    import oracle
+    threads = oracle.max_threads()
+    k_s = min(B.shape[1], 64 * threads)
+    n = L.shape[0]
+    t0 = time.perf_counter()
+    oracle.trsm(L, B[:, :k_s])
+    dt = time.perf_counter() - t0
+    return {"value": n * n * k_s / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"n={n}, first k={k_s} of the {B.shape[1]} columns of the same L and B "
+                      f"(columns are independent), binary64 forward substitution"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--k", type=int, default=16384)
+    ap.add_argument("--n0", type=int, default=0)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the solve is measured on one MI355X; see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1612_01855_amd import inputs as gen
+    from paper_1612_01855_amd import trsm as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, k = args.n, args.k
+    log(f"generating L ({n}x{n}) and B ({n}x{k}), seed {args.seed}")
+    L, B = gen.easy_system(n, k, args.seed)
+    dt = torch.float32 if args.precision == "f32" else torch.float64
+    Ld = torch.from_numpy(L).to(dev, dt)
+    Bd = torch.from_numpy(B).to(dev, dt)
+    Xd = torch.empty_like(Bd)
+    torch.cuda.synchronize()
+
+    solver = T.Solver.create(n, k, args.precision, args.n0, 0, device=dev)
+    info = solver.info
+    stream = torch.cuda.current_stream(dev)
+    log(f"plan: n0={info.n0} m={info.m} (paper rule n0={info.n0_paper_rule}); "
+        f"Linv {info.linv_bytes / 2**20:.0f} MiB, workspace {info.workspace_bytes / 2**20:.0f} MiB")
+
+    def step():
+        solver.invert(Ld)
+        solver.solve(Ld, Bd, Xd)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    st, idx = solver.last_error()
+    assert st == T.OK, f"singular diagonal at {idx}"
+
+    T.trsm_plan_set_timing(solver.plan, True)
+    T.trsm_plan_timing(solver.plan)           # clear
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    launches, gemm_ms, gemm_flops = T.trsm_plan_timing(solver.plan)
+    T.trsm_plan_set_timing(solver.plan, False)
+    ms_step = ms_total / args.steps
+    flops_step = float(n) * n * k
+    tflops = flops_step / (ms_step * 1e-3) / 1e12
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {tflops:.2f} TFLOP/s (n^2 k)")
+
+    # untimed: untouched-step time without event brackets (for reference)
+    workload = f"trsm_{args.precision}_n{n}_k{k}"
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    peak = PEAK[args.precision]
+    traffic = traffic_from_profiles(workload)
+    roofline = {"bound": "mfma", "kernel": "gemm_kernel (all product launches of a step)",
+                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "launches_per_step": launches // args.steps,
+                "avg_launch_ms": round(gemm_ms / max(launches, 1), 4),
+                "algorithmic_flops_per_launch": gemm_flops / max(launches, 1)}
+
+    # correctness of the benchmarked X: binary64 residual on the GPU
+    check = {}
+    if args.precision == "f64":
+        R = torch.empty_like(Bd)
+        ws = torch.empty(T.trsm_residual_workspace_bytes(n, k), dtype=torch.uint8, device=dev)
+        rn, xn, rmax = T.trsm_residual(n, k, Ld.data_ptr(), n, Xd.data_ptr(), k, Bd.data_ptr(), k,
+                                       R.data_ptr(), k, ws.data_ptr(), stream.cuda_stream)
+        lnorm = float(torch.linalg.norm(torch.tril(Ld)).item())
+        check = {"backward_error": rn / (lnorm * xn)}
+        del R, ws
+        log(f"backward error {check['backward_error']:.2e}")
+
+    mixed = {}
+    if not args.no_mixed and args.precision == "f64":
+        for prec in ("bf16", "f16"):
+            try:
+                s2 = T.Solver.create(n, k, prec, args.n0, 0, device=dev)
+                Xm = torch.empty_like(Bd)
+                s2.invert(Ld)
+                inf = T.Info()
+                s2.solve(Ld, Bd, Xm, info=inf)         # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = 2
+                for _ in range(reps):
+                    s2.invert(Ld)
+                    s2.solve(Ld, Bd, Xm, info=inf)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                diff = float(torch.linalg.norm(Xm - Xd).item() / torch.linalg.norm(Xd).item())
+                mixed[prec] = {"ms_per_solve": round(ms, 3),
+                               "tflops_n2k": round(flops_step / (ms * 1e-3) / 1e12, 3),
+                               "speedup_vs_f64": round(ms_step / ms, 3),
+                               "corrections": inf.iterations, "converged": bool(inf.converged),
+                               "backward_error": inf.backward_error,
+                               "unrefined_error_est": inf.unrefined_error,
+                               "rel_diff_vs_f64_solve": diff}
+                log(f"mixed {prec}: {ms:.2f} ms/solve, {inf.iterations} corrections, diff {diff:.1e}")
+                del Xm
+                s2.close()
+                torch.cuda.empty_cache()
+            except Exception as e:  # report, never hide
+                mixed[prec] = {"error": str(e)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a column sample")
+        cpu = cpu_baseline(L, B.astype(np.float32).astype(np.float64) if args.precision == "f32" else B)
+        log(f"oracle: {cpu['value'] * 1e3:.2f} GFLOP/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "k": k, "n0": info.n0, "m": info.m,
+                   "n0_paper_rule": info.n0_paper_rule, "precision": args.precision,
+                   "L": "diag U[1,2], strict lower U[-1,1]/n", "B": "N(0,1)", "seed": args.seed,
+                   "step": "trsm_invert_diag + trsm_solve (right-looking sweep)",
+                   "inversion_flops_per_step": info.inv_flops},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

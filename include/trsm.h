@@ -169,6 +169,19 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl,
                           double* R, int64_t ldr, void* workspace, double* norms,
                           void* stream);
 
+/*
+ * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes
+ * every matrix-core product launched by trsm_invert_diag and trsm_solve with
+ * this plan record a pair of hipEvents around itself on the call's stream
+ * (the plan creates and owns the events; recording adds a few microseconds
+ * per launch).  trsm_plan_timing waits for the recorded events, returns the
+ * number of launches, their summed duration in milliseconds and their
+ * summed algorithmic flops (2MNK per dense product, M(M+1)N when a square
+ * factor is triangular), and clears the record.  Host only; blocking.
+ */
+trsm_status trsm_plan_set_timing(trsm_plan_t plan, int enable);
+trsm_status trsm_plan_timing(trsm_plan_t plan, int64_t* launches, double* ms, double* flops);
+
 #ifdef __cplusplus
 }
 #endif

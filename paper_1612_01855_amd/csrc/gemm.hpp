@@ -57,9 +57,23 @@ template <> struct VecOf<float> { typedef float T2 __attribute__((ext_vector_typ
 template <> struct VecOf<bf16_t> { typedef __bf16 T2 __attribute__((ext_vector_type(8))); };
 template <> struct VecOf<f16_t> { typedef _Float16 T2 __attribute__((ext_vector_type(8))); };
 
+// Buffer descriptor word 3 for the gfx9 family (raw, untyped loads).
+constexpr int kBufWord3 = 0x00020000;
+// Offsets at or above this value read as zero (outside the descriptor).
+constexpr int kBufOOB = 0x7FFFFFF0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, kBufOOB, kBufWord3);
+}
+
+template <typename V>
+__device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
-__global__ __launch_bounds__(WGM * WGN * 64)
+__global__ __launch_bounds__(WGM * WGN * 64, 2)
 void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
@@ -68,20 +82,25 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int VEC = 16 / sizeof(TIn);         // elements per 16-byte vector
   constexpr int BK = 128 / sizeof(TIn);         // one 128-byte row segment per chunk
-  constexpr int KL = BK / 4;                    // contiguous k per lane per chunk
+  constexpr int KL = BK / 4;                    // contiguous k per lane group per chunk
   constexpr int STEPS = KL / MF::kPerLane;      // MFMAs per 16x16 tile per chunk
-  constexpr int LDS_S = BK + VEC;               // padded LDS row stride (elements)
   constexpr int WTM = BM / WGM, WTN = BN / WGN; // wave tile
   constexpr int TM = WTM / 16, TN = WTN / 16;   // MFMA tiles per wave
-  constexpr int VPR = BK / VEC;                 // vectors per k-row segment
+  // LDS: A as [row][k]; B as [k][n] (row-major B) or [n][k] (BKMAJOR).
+  constexpr int LDA_S = BK + VEC;
+  constexpr int LDB_S = BKMAJOR ? (BK + VEC) : (BN + VEC);
+  constexpr int B_ELEMS = BKMAJOR ? BN * LDB_S : BK * LDB_S;
+  constexpr int VPR = BK / VEC;                 // vectors per k segment of one A row
   constexpr int A_ITERS = BM * VPR / NT;
-  constexpr int B_ITERS = BN * VPR / NT;
+  constexpr int B_VPL = BKMAJOR ? VPR : BN / VEC;   // vectors per stored B line
+  constexpr int B_ITERS = (BKMAJOR ? BN * VPR : BK * (BN / VEC)) / NT;
   static_assert(A_ITERS * NT == BM * VPR, "A tile load must divide evenly");
-  static_assert(B_ITERS * NT == BN * VPR, "B tile load must divide evenly");
+  static_assert(B_ITERS * NT == (BKMAJOR ? BN * VPR : BK * (BN / VEC)), "B tile load must divide evenly");
+  static_assert(BKMAJOR || MF::kPerLane == 1, "row-major B needs a one-k-per-lane instruction");
   constexpr int GROUP_M = 8;
 
-  __shared__ __attribute__((aligned(16))) TIn As[2][BM * LDS_S];
-  __shared__ __attribute__((aligned(16))) TIn Bs[2][BN * LDS_S];
+  __shared__ __attribute__((aligned(16))) TIn As[2][BM * LDA_S];
+  __shared__ __attribute__((aligned(16))) TIn Bs[2][B_ELEMS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -95,6 +114,7 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   const TIn* __restrict__ A = p.A + zo * p.sa_o + zi * p.sa_i;
   const TIn* __restrict__ B = p.B + zo * p.sb_o + zi * p.sb_i;
   const int M = p.M, N = p.N, K = p.K;
+  const int64_t lda = p.lda, ldb = p.ldb;
 
   // ---- tile coordinates (XCD-aware, grouped) -----------------------------
   const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
@@ -125,27 +145,27 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = Acc(0);
 
-  // ---- global -> register staging --------------------------------------
+  // ---- global -> register staging (no per-lane branches) -------------------
   V16 ra[A_ITERS], rb[B_ITERS];
 
   auto load_a = [&](int k0) {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(A + (int64_t)r0 * lda + k0);
 #pragma unroll
     for (int it = 0; it < A_ITERS; ++it) {
       const int idx = tid + it * NT;
       const int row = idx / VPR, kv = (idx % VPR) * VEC;
       const int gr = r0 + row, gk = k0 + kv;
       V16 v;
-      if (ALIGNED && gr < M && gk + VEC <= K) {
-        v = *reinterpret_cast<const V16*>(A + (int64_t)gr * p.lda + gk);
+      if constexpr (ALIGNED) {
+        const bool ok = gr < M && gk < K;
+        v = buf_load16<V16>(rs, ok ? (int)((row * lda + kv) * (int64_t)sizeof(TIn)) : kBufOOB);
       } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          v[e] = (gr < M && gk + e < K) ? A[(int64_t)gr * p.lda + gk + e] : TIn(0);
-      }
-      if (a_lower) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (gk + e > gr) v[e] = TIn(0);
+        for (int e = 0; e < VEC; ++e) {
+          const bool ok = gr < M && gk + e < K;
+          const TIn x = A[ok ? (int64_t)gr * lda + gk + e : 0];
+          v[e] = ok ? x : TIn(0);
+        }
       }
       ra[it] = v;
     }
@@ -156,61 +176,71 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
       const int idx = tid + it * NT;
       V16 v;
       if constexpr (BKMAJOR) {
-        // B stored N x K: a row of the stored matrix is a column of B.
+        // B stored N x K: a stored row is a column of B.
         const int col = idx / VPR, kv = (idx % VPR) * VEC;
         const int gc = c0 + col, gk = k0 + kv;
-        if (ALIGNED && gc < N && gk + VEC <= K) {
-          v = *reinterpret_cast<const V16*>(B + (int64_t)gc * p.ldb + gk);
+        if constexpr (ALIGNED) {
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(B + (int64_t)c0 * ldb + k0);
+          const bool ok = gc < N && gk < K;
+          v = buf_load16<V16>(rs, ok ? (int)((col * ldb + kv) * (int64_t)sizeof(TIn)) : kBufOOB);
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            v[e] = (gc < N && gk + e < K) ? B[(int64_t)gc * p.ldb + gk + e] : TIn(0);
-        }
-        if (b_lower) {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (gk + e < gc) v[e] = TIn(0);
+          for (int e = 0; e < VEC; ++e) {
+            const bool ok = gc < N && gk + e < K;
+            const TIn x = B[ok ? (int64_t)gc * ldb + gk + e : 0];
+            v[e] = ok ? x : TIn(0);
+          }
         }
       } else {
-        // B stored K x N: vectors run along n; (BK rows) x (BN/VEC vectors).
-        constexpr int VPC = BN / VEC;
-        const int krow = idx / VPC, cv = (idx % VPC) * VEC;
+        // B stored K x N: BK rows of BN/VEC vectors.
+        const int krow = idx / B_VPL, cv = (idx % B_VPL) * VEC;
         const int gk = k0 + krow, gc = c0 + cv;
-        if (ALIGNED && gk < K && gc + VEC <= N) {
-          v = *reinterpret_cast<const V16*>(B + (int64_t)gk * p.ldb + gc);
+        if constexpr (ALIGNED) {
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(B + (int64_t)k0 * ldb + c0);
+          const bool ok = gk < K && gc < N;
+          v = buf_load16<V16>(rs, ok ? (int)((krow * ldb + cv) * (int64_t)sizeof(TIn)) : kBufOOB);
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            v[e] = (gk < K && gc + e < N) ? B[(int64_t)gk * p.ldb + gc + e] : TIn(0);
-        }
-        if (b_lower) {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (gk < gc + e) v[e] = TIn(0);
+          for (int e = 0; e < VEC; ++e) {
+            const bool ok = gk < K && gc + e < N;
+            const TIn x = B[ok ? (int64_t)gk * ldb + gc + e : 0];
+            v[e] = ok ? x : TIn(0);
+          }
         }
       }
       rb[it] = v;
     }
   };
-  auto store_ab = [&](int buf) {
+  // Triangular masks are applied when the staged data is written to LDS, so
+  // that the global loads of the next chunk stay in flight during the MFMAs.
+  auto store_ab = [&](int buf, int k0) {
 #pragma unroll
     for (int it = 0; it < A_ITERS; ++it) {
       const int idx = tid + it * NT;
       const int row = idx / VPR, kv = (idx % VPR) * VEC;
-      *reinterpret_cast<V16*>(&As[buf][row * LDS_S + kv]) = ra[it];
+      V16 v = ra[it];
+      if (a_lower) {
+        const int gr = r0 + row, gk = k0 + kv;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = (gk + e > gr) ? TIn(0) : v[e];
+      }
+      *reinterpret_cast<V16*>(&As[buf][row * LDA_S + kv]) = v;
     }
 #pragma unroll
     for (int it = 0; it < B_ITERS; ++it) {
       const int idx = tid + it * NT;
-      if constexpr (BKMAJOR) {
-        const int col = idx / VPR, kv = (idx % VPR) * VEC;
-        *reinterpret_cast<V16*>(&Bs[buf][col * LDS_S + kv]) = rb[it];
-      } else {
-        constexpr int VPC = BN / VEC;
-        const int krow = idx / VPC, cv = (idx % VPC) * VEC;
+      const int line = idx / B_VPL, vo = (idx % B_VPL) * VEC;
+      V16 v = rb[it];
+      if (b_lower) {
+        // BKMAJOR: line = column, vo = k offset; else line = k row, vo = column offset
+        const int gc = c0 + (BKMAJOR ? line : vo), gk = k0 + (BKMAJOR ? vo : line);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) Bs[buf][(cv + e) * LDS_S + krow] = rb[it][e];
+        for (int e = 0; e < VEC; ++e) {
+          const bool zero = BKMAJOR ? (gk + e < gc) : (gk < gc + e);
+          v[e] = zero ? TIn(0) : v[e];
+        }
       }
+      *reinterpret_cast<V16*>(&Bs[buf][line * LDB_S + vo]) = v;
     }
   };
 
@@ -218,7 +248,7 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   if (nchunks > 0) {
     load_a(kbeg);
     load_b(kbeg);
-    store_ab(0);
+    store_ab(0, kbeg);
     __syncthreads();
     for (int c = 0; c < nchunks; ++c) {
       const int buf = c & 1;
@@ -227,43 +257,29 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
         load_a(kbeg + (c + 1) * BK);
         load_b(kbeg + (c + 1) * BK);
       }
-      // fragments: lane group g owns k = g*KL .. g*KL+KL-1 of the chunk
-      V16 fa[TM][2], fb[TN][2];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const TIn* src = &As[buf][(wm * WTM + i * 16 + gi) * LDS_S + g * KL];
-        fa[i][0] = *reinterpret_cast<const V16*>(src);
-        fa[i][1] = *reinterpret_cast<const V16*>(src + VEC);
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const TIn* src = &Bs[buf][(wn * WTN + j * 16 + gi) * LDS_S + g * KL];
-        fb[j][0] = *reinterpret_cast<const V16*>(src);
-        fb[j][1] = *reinterpret_cast<const V16*>(src + VEC);
-      }
+      const TIn* as = As[buf];
+      const TIn* bs = Bs[buf];
 #pragma unroll
       for (int s = 0; s < STEPS; ++s) {
+        // lane group g feeds k = g*KL + s*kPerLane ... + kPerLane - 1
+        const int kk = g * KL + s * MF::kPerLane;
+        typename MF::Frag fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          typename MF::Frag a;
-          if constexpr (MF::kPerLane == 1) {
-            a = fa[i][s / VEC][s % VEC];
-          } else {
-            a = fa[i][s];
-          }
+        for (int i = 0; i < TM; ++i)
+          fa[i] = *reinterpret_cast<const typename MF::Frag*>(&as[(wm * WTM + i * 16 + gi) * LDA_S + kk]);
 #pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            typename MF::Frag b;
-            if constexpr (MF::kPerLane == 1) {
-              b = fb[j][s / VEC][s % VEC];
-            } else {
-              b = fb[j][s];
-            }
-            acc[i][j] = MF::mma(a, b, acc[i][j]);
-          }
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (BKMAJOR)
+            fb[j] = *reinterpret_cast<const typename MF::Frag*>(&bs[(wn * WTN + j * 16 + gi) * LDB_S + kk]);
+          else
+            fb[j] = bs[kk * LDB_S + wn * WTN + j * 16 + gi];
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[i], fb[j], acc[i][j]);
       }
-      if (more) store_ab(buf ^ 1);
+      if (more) store_ab(buf ^ 1, kbeg + (c + 1) * BK);
       __syncthreads();
     }
   }
@@ -310,9 +326,13 @@ inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int ba
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
   constexpr int VEC = 16 / sizeof(TIn);
   auto al = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
+  constexpr int BK = 128 / sizeof(TIn);
+  const int64_t span_a = (int64_t)BM * p.lda * (int64_t)sizeof(TIn);
+  const int64_t span_b = (int64_t)(BKMAJOR ? BN : BK) * p.ldb * (int64_t)sizeof(TIn);
   const bool aligned = al(p.A) && al(p.B) && p.lda % VEC == 0 && p.ldb % VEC == 0 &&
                        p.sa_o % VEC == 0 && p.sa_i % VEC == 0 && p.sb_o % VEC == 0 &&
-                       p.sb_i % VEC == 0;
+                       p.sb_i % VEC == 0 && p.K % VEC == 0 && (BKMAJOR || p.N % VEC == 0) &&
+                       span_a < kBufOOB && span_b < kBufOOB;
   const int64_t tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
   dim3 grid((unsigned)tiles, 1, (unsigned)batch);
   dim3 block(WGM * WGN * 64);

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "gemm.hpp"
@@ -65,6 +66,75 @@ inline bool is_mixed(trsm_precision p) { return p == TRSM_MIXED_BF16 || p == TRS
 
 }  // namespace
 
+// Optional per-plan timing of the matrix-core launches: each launch is
+// bracketed by two hipEvents on its stream; the elapsed times are summed when
+// the host asks for them (after synchronising).
+struct LaunchTimer {
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;   // 2 per record, reused
+  std::vector<double> flops;    // algorithmic flops per record
+  size_t used = 0;
+
+  hipError_t begin(hipStream_t s) {
+    if (2 * used + 2 > ev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+      }
+    }
+    return hipEventRecord(ev[2 * used], s);
+  }
+  hipError_t end(hipStream_t s, double f) {
+    hipError_t r = hipEventRecord(ev[2 * used + 1], s);
+    if (r != hipSuccess) return r;
+    if (flops.size() <= used) flops.resize(used + 1);
+    flops[used] = f;
+    ++used;
+    return hipSuccess;
+  }
+  void release() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    flops.clear();
+    used = 0;
+  }
+};
+
+namespace {
+thread_local LaunchTimer* g_timer = nullptr;
+
+struct TimerScope {
+  LaunchTimer* prev;
+  explicit TimerScope(LaunchTimer* t) : prev(g_timer) { g_timer = (t && t->enabled) ? t : nullptr; }
+  ~TimerScope() { g_timer = prev; }
+};
+
+template <typename F>
+hipError_t timed(double flops, hipStream_t s, F&& launch) {
+  LaunchTimer* t = g_timer;
+  if (!t) return launch();
+  hipError_t e = t->begin(s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return t->end(s, flops);
+}
+
+// Algorithmic flops of one (batched) product: 2MNK, or M(M+1)N when A is
+// square lower triangular, or MN(N+1) when B is.
+template <typename P>
+double gemm_flops(const P& p, int batch) {
+  const double M = p.M, N = p.N, K = p.K;
+  double f;
+  if ((p.flags & G_A_LOWER) && p.M == p.K) f = M * (M + 1) * N;
+  else if ((p.flags & G_B_LOWER) && p.K == p.N) f = M * N * (N + 1);
+  else f = 2.0 * M * N * K;
+  return f * batch;
+}
+}  // namespace
+
 struct trsm_plan_s {
   int64_t n = 0, k = 0, n0 = 1, m = 0, leaf = 1, n0_paper = 1;
   trsm_precision prec = TRSM_F64;
@@ -76,6 +146,7 @@ struct trsm_plan_s {
   size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_part = 0, ws_norm = 0;
   size_t ws_bytes = 0;
   unsigned long long* d_bad = nullptr;   // first singular row (device word)
+  LaunchTimer timer;
 };
 
 // ---------------------------------------------------------------------------
@@ -131,7 +202,8 @@ template <typename T>
 struct Gemm {
   using P = GemmParams<T, T, T, float>;
   static hipError_t run(const P& p, int batch, hipStream_t s) {
-    return launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s);
+    return timed(gemm_flops(p, batch), s,
+                 [&] { return launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s); });
   }
 };
 
@@ -277,7 +349,9 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.C2 = XlowT + r0; p.ldc2 = n;
       p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
       p.flags = G_A_LOWER | G_C2_T;
-      TRSM_HIP((launch_gemm<float, float, float, TL, 128, 128, 2, 2, false>(p, 1, s)));
+      TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
+        return launch_gemm<float, float, float, TL, 128, 128, 2, 2, false>(p, 1, s);
+      }));
     }
     if (i + 1 < m) {
       const int64_t t0 = r0 + n0, rows = n - t0;
@@ -290,7 +364,9 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.M = (int)rows; p.N = (int)k; p.K = (int)sz;
       p.alpha = -1.0; p.beta = 1.0;
       p.flags = G_BETA | G_ROWSCALE;
-      TRSM_HIP((launch_gemm<TL, float, float, float, 128, 128, 2, 2, true>(p, 1, s)));
+      TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
+        return launch_gemm<TL, float, float, float, 128, 128, 2, 2, true>(p, 1, s);
+      }));
     }
   }
   return TRSM_OK;
@@ -500,6 +576,7 @@ trsm_status trsm_plan_get_info(trsm_plan_t P, trsm_plan_info* info) {
 trsm_status trsm_plan_destroy(trsm_plan_t P) {
   if (!P) return TRSM_OK;
   if (P->d_bad) (void)hipFree(P->d_bad);
+  P->timer.release();
   delete P;
   return TRSM_OK;
 }
@@ -511,6 +588,7 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
   if (!L || !Linv || ldl < P->n) return TRSM_EINVAL;
   if (((uintptr_t)Linv) % kAlign) return TRSM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  TimerScope timer_scope(&P->timer);
   char* base = (char*)Linv;
   double* L64 = (double*)(base + P->off_linv64);
   const int64_t n = P->n, n0 = P->n0, m = P->m;
@@ -588,6 +666,7 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   if (ranges_overlap(B, bbytes, X, xbytes) && !(B == X && ldb == ldx)) return TRSM_EINVAL;
   if (is_mixed(P->prec) && B == X && !(P->flags & TRSM_FLAG_NO_REFINE)) return TRSM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  TimerScope timer_scope(&P->timer);
   const char* lb = (const char*)Linv;
   char* ws = (char*)workspace;
   if (rec) {
@@ -646,6 +725,31 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl, co
   norms[0] = sqrt(h[0]);
   norms[1] = sqrt(h[2]);
   norms[2] = h[1];
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_set_timing(trsm_plan_t P, int enable) {
+  if (!P) return TRSM_EINVAL;
+  P->timer.enabled = enable != 0;
+  P->timer.used = 0;
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_timing(trsm_plan_t P, int64_t* launches, double* ms, double* flops) {
+  if (!P || !launches || !ms || !flops) return TRSM_EINVAL;
+  LaunchTimer& t = P->timer;
+  double tot_ms = 0.0, tot_fl = 0.0;
+  for (size_t i = 0; i < t.used; ++i) {
+    TRSM_HIP(hipEventSynchronize(t.ev[2 * i + 1]));
+    float e = 0.f;
+    TRSM_HIP(hipEventElapsedTime(&e, t.ev[2 * i], t.ev[2 * i + 1]));
+    tot_ms += e;
+    tot_fl += t.flops[i];
+  }
+  *launches = (int64_t)t.used;
+  *ms = tot_ms;
+  *flops = tot_fl;
+  t.used = 0;
   return TRSM_OK;
 }
 

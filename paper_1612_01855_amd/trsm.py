@@ -47,7 +47,8 @@ class Info(ctypes.Structure):
 
 EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
-           "trsm_residual_workspace_bytes", "trsm_residual"]
+           "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
+           "trsm_plan_timing"]
 
 
 class TrsmError(RuntimeError):
@@ -84,6 +85,11 @@ def _load():
     lib.trsm_residual.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
                                   ctypes.POINTER(ctypes.c_double), vp]
     lib.trsm_residual.restype = i32
+    lib.trsm_plan_set_timing.argtypes = [vp, i32]
+    lib.trsm_plan_set_timing.restype = i32
+    lib.trsm_plan_timing.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.trsm_plan_timing.restype = i32
     return lib
 
 
@@ -148,6 +154,18 @@ def trsm_residual(n: int, k: int, L: int, ldl: int, X: int, ldx: int, B: int, ld
     _check(_lib.trsm_residual(n, k, L, ldl, X, ldx, B, ldb, R, ldr, workspace, norms, stream),
            "trsm_residual")
     return tuple(norms)
+
+
+def trsm_plan_set_timing(plan: int, enable: bool = True) -> None:
+    _check(_lib.trsm_plan_set_timing(plan, 1 if enable else 0), "trsm_plan_set_timing")
+
+
+def trsm_plan_timing(plan: int):
+    """(launches, milliseconds, algorithmic flops) of the timed launches."""
+    n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.trsm_plan_timing(plan, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)),
+           "trsm_plan_timing")
+    return n.value, ms.value, fl.value
 
 
 # ---- torch-tensor convenience (memory ownership only) ------------------------
