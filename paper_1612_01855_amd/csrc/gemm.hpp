@@ -20,8 +20,13 @@
 // Work decomposition: a workgroup of WGM x WGN waves owns a BM x BN tile;
 // each wave owns (BM/WGM) x (BN/WGN) made of 16x16 MFMA tiles.  K advances in
 // chunks of BK with two LDS buffers and a register prefetch of the next
-// chunk, one barrier per chunk.  Workgroup ids are remapped so that
-// consecutive tiles share an XCD (and its L2), in groups of GROUP_M row tiles.
+// chunk, one barrier per chunk.  Tiles are visited in groups of GROUP_M row
+// tiles (column-major inside a group) so that concurrently running
+// workgroups share A and B panels in L2.  Workgroup ids are NOT regrouped
+// per XCD by default: the hardware deals consecutive ids to the XCDs in turn,
+// which spreads the uneven tile costs of a triangular product evenly over the
+// eight XCDs (giving each XCD a contiguous range of tiles made the
+// lower-triangular residual twice as slow).
 #pragma once
 
 #include "common.hpp"
@@ -72,7 +77,8 @@ __device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, int off) {
 }
 
 template <typename TIn, typename TCin, typename TCout, typename TC2,
-          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
+          int GROUP_M = 8, bool XCD_REMAP = false>
 __global__ __launch_bounds__(WGM * WGN * 64, 2)
 void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   using MF = Mfma<TIn>;
@@ -97,7 +103,6 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   static_assert(A_ITERS * NT == BM * VPR, "A tile load must divide evenly");
   static_assert(B_ITERS * NT == (BKMAJOR ? BN * VPR : BK * (BN / VEC)), "B tile load must divide evenly");
   static_assert(BKMAJOR || MF::kPerLane == 1, "row-major B needs a one-k-per-lane instruction");
-  constexpr int GROUP_M = 8;
 
   __shared__ __attribute__((aligned(16))) TIn As[2][BM * LDA_S];
   __shared__ __attribute__((aligned(16))) TIn Bs[2][B_ELEMS];
@@ -120,7 +125,7 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
   int bid = blockIdx.x;
   const int nwg = gridDim.x;
-  if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  if (XCD_REMAP && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
   const int per_group = GROUP_M * ntn;
   const int grp = bid / per_group;
   const int first_m = grp * GROUP_M;
