@@ -170,6 +170,113 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl,
                           void* stream);
 
 /*
+ * Batches -- many independent systems L_p X_p = B_p of uneven n_p and k_p
+ * solved together.  Every phase of the blocked sweep of Alg. It-Inv-TRSM
+ * (the diagonal apply of step i, the trailing update of step i) is ONE
+ * grouped launch over the tiles of every system that has that phase, so the
+ * whole batch takes 2*max(m_p) - 1 launches; systems with fewer blocks drop
+ * out of later phases.  Each system's result is computed by the same tiles
+ * in the same order as when it is solved alone, so it is bitwise independent
+ * of the rest of the batch.
+ *
+ *  items[p]: n, k; L (device, lower triangle read, ldl >= n); Linv (device,
+ *  filled by trsm_invert_diag with a plan of this n, the same precision and
+ *  the same n0; 256-byte aligned); B (read) and X (written), ld >= k, X must
+ *  not overlap B.  prec: TRSM_F64 or TRSM_F32 (element type of L, B, X).
+ *  n0: power of two, the same for every item.
+ *
+ * trsm_batch_create copies the item array (host only, no device work).
+ * trsm_batch_workspace_bytes: device workspace trsm_batch_run needs.
+ * trsm_batch_run enqueues the batch on `stream` (asynchronous).  The launch
+ *  table is written at the head of `workspace` (256-byte aligned).  With
+ *  use_graph != 0 the table upload and all launches are captured into a
+ *  hipGraph on the first call and replayed by later calls that pass the same
+ *  workspace and stream (the items' buffers must then be unchanged
+ *  addresses; their contents may change).
+ * trsm_batch_destroy releases the handle (and its graph).
+ */
+typedef struct trsm_batch_item {
+  int64_t n, k;
+  const void* L;
+  int64_t ldl;
+  const void* Linv;
+  const void* B;
+  int64_t ldb;
+  void* X;
+  int64_t ldx;
+} trsm_batch_item;
+
+typedef struct trsm_batch_s* trsm_batch_t;
+
+trsm_status trsm_batch_create(int32_t count, const trsm_batch_item* items, trsm_precision prec,
+                              int64_t n0, trsm_batch_t* out);
+trsm_status trsm_batch_workspace_bytes(trsm_batch_t batch, size_t* bytes);
+trsm_status trsm_batch_run(trsm_batch_t batch, void* workspace, void* stream, int32_t use_graph);
+trsm_status trsm_batch_destroy(trsm_batch_t batch);
+
+/*
+ * Serving -- continuous batching of solves against resident factors.
+ *
+ * trsm_server_create(hbm_budget, max_slots, n0, &srv): the server allocates
+ *  ONE device block of hbm_budget bytes on the current device and never more;
+ *  factors and in-flight requests are carved from it ("admission by HBM
+ *  budget").  At most max_slots requests are in flight.  n0 (power of two)
+ *  is the diagonal block size used for every factor.  A worker thread and
+ *  four streams (default priority) are created.  Thread-safe afterwards.
+ * trsm_server_register_L(srv, L, n, ldl, &l_id): copies the binary64 lower
+ *  triangle of L (device pointer) into the server, makes a binary32 copy and
+ *  inverts its diagonal blocks (Alg. Diagonal-Inverter) once; blocking.
+ *  TRSM_ENOMEM if it does not fit the budget, TRSM_ESINGULAR for a zero or
+ *  non-finite diagonal.
+ * trsm_serve_submit(srv, l_id, B, k, ldb, X, ldx, &ticket): never blocks.
+ *  B (read) and X (written) are caller-owned binary64 device matrices (n x k,
+ *  row-major) that must stay valid until the ticket is DONE or ERROR.  The
+ *  request waits until its workspace (32 n k bytes, k rounded up to 4) fits the budget
+ *  and a slot is free, then joins the next batch, which runs on one of the
+ *  server's streams while earlier batches may still be running.  Each
+ *  request is solved with binary32 sweeps and one refinement step with a
+ *  binary64 residual; its result does not depend on the other requests.
+ *  A request that can never fit fails with TRSM_ENOMEM.
+ * trsm_serve_poll(srv, ticket, &state, &latency_us): never blocks.  A DONE
+ *  or ERROR ticket is reported once (then forgotten); latency is submit ->
+ *  completion observed by the worker, in microseconds.  Returns the
+ *  request's error status for ERROR.
+ * trsm_server_stats / trsm_server_reset_stats: counters, p50/p99/mean
+ *  latency of completed requests, n^2 k flops completed, memory in use.
+ * trsm_server_destroy: waits for queued and in-flight work, frees everything.
+ */
+typedef enum trsm_req_state {
+  TRSM_REQ_PENDING = 0,
+  TRSM_REQ_RUNNING = 1,
+  TRSM_REQ_DONE = 2,
+  TRSM_REQ_ERROR = 3,
+  TRSM_REQ_UNKNOWN = 4
+} trsm_req_state;
+
+typedef struct trsm_serve_stats {
+  uint64_t submitted, completed, failed, batches;
+  double p50_us, p99_us, mean_us;
+  double flops_done;       /* sum of n^2 k over completed requests */
+  double wall_s;           /* first submit to last completion */
+  size_t hbm_budget, hbm_in_use, resident_bytes;
+  int32_t queue_depth, in_flight, max_in_flight, factors;
+} trsm_serve_stats;
+
+typedef struct trsm_server_s* trsm_server_t;
+
+trsm_status trsm_server_create(size_t hbm_budget, int32_t max_slots, int64_t n0,
+                               trsm_server_t* out);
+trsm_status trsm_server_register_L(trsm_server_t srv, const double* L, int64_t n, int64_t ldl,
+                                   int32_t* l_id);
+trsm_status trsm_serve_submit(trsm_server_t srv, int32_t l_id, const double* B, int64_t k,
+                              int64_t ldb, double* X, int64_t ldx, uint64_t* ticket);
+trsm_status trsm_serve_poll(trsm_server_t srv, uint64_t ticket, trsm_req_state* state,
+                            double* latency_us);
+trsm_status trsm_server_stats(trsm_server_t srv, trsm_serve_stats* stats);
+trsm_status trsm_server_reset_stats(trsm_server_t srv);
+trsm_status trsm_server_destroy(trsm_server_t srv);
+
+/*
  * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes
  * every matrix-core product launched by trsm_invert_diag and trsm_solve with
  * this plan record a pair of hipEvents around itself on the call's stream

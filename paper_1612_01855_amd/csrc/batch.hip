@@ -1,0 +1,383 @@
+// Grouped launches for batches of triangular solves, and the C ABI
+// trsm_batch_* (see include/trsm.h).
+#include "batch.hpp"
+
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/trsm.h"
+#include "kernels.hpp"
+
+namespace trsm {
+
+namespace {
+
+// Grouped elementwise kernel: entry e owns workgroups [start[e], start[e+1]),
+// each workgroup converts kEwChunk consecutive elements (row-major order) of
+// its matrix.
+__global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restrict__ entries,
+                                                         const int* __restrict__ start, int n) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const EwEntry& e = entries[lo];
+  const int64_t total = (int64_t)e.rows * e.cols;
+  const int64_t base = (int64_t)(b - start[lo]) * kEwChunk;
+  for (int64_t i = base + threadIdx.x; i < min(total, base + kEwChunk); i += 256) {
+    const int64_t r = i / e.cols, c = i % e.cols;
+    const bool pad = c >= e.valid_cols;
+    switch (e.op) {
+      case EW_F64_TO_F32:
+        static_cast<float*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0f
+                : static_cast<float>(e.scale * static_cast<const double*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F32_TO_F64_SET:
+        static_cast<double*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0 : e.scale * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F32_TO_F64_ADD:
+        if (!pad)
+          static_cast<double*>(e.dst)[r * e.ldd + c] +=
+              e.scale * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F64_COPY:
+        static_cast<double*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0 : e.scale * static_cast<const double*>(e.src)[r * e.lds + c];
+        break;
+      default:
+        static_cast<float*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0f : static_cast<float>(e.scale) * static_cast<const float*>(e.src)[r * e.lds + c];
+        break;
+    }
+  }
+}
+
+constexpr int kBM = 128, kBN = 128;
+
+}  // namespace
+
+void LaunchList::clear() {
+  host_.clear();
+  phases_.clear();
+}
+
+template <typename T>
+size_t LaunchList::append(const T* data, size_t n) {
+  size_t off = (host_.size() + 15) / 16 * 16;
+  host_.resize(off + n * sizeof(T));
+  if (n) memcpy(host_.data() + off, data, n * sizeof(T));
+  return off;
+}
+
+namespace {
+template <typename P>
+std::vector<int> gemm_starts(const std::vector<P>& e, int* total) {
+  std::vector<int> st(e.size() + 1, 0);
+  for (size_t i = 0; i < e.size(); ++i) {
+    const int64_t tiles = ceil_div(e[i].M, kBM) * ceil_div(e[i].N, kBN);
+    st[i + 1] = st[i] + (int)tiles;
+  }
+  *total = st.back();
+  return st;
+}
+}  // namespace
+
+void LaunchList::add_gemm64(const std::vector<GemmP64>& entries) {
+  if (entries.empty()) return;
+  Phase ph{};
+  ph.kind = PH_GEMM_F64;
+  ph.count = (int)entries.size();
+  ph.aligned = true;
+  for (const auto& e : entries) ph.aligned &= gemm_aligned<double, kBM, kBN, false>(e);
+  std::vector<int> st = gemm_starts(entries, &ph.total);
+  ph.entries_off = append(entries.data(), entries.size());
+  ph.start_off = append(st.data(), st.size());
+  if (ph.total > 0) phases_.push_back(ph);
+}
+
+void LaunchList::add_gemm32(const std::vector<GemmP32>& entries) {
+  if (entries.empty()) return;
+  Phase ph{};
+  ph.kind = PH_GEMM_F32;
+  ph.count = (int)entries.size();
+  ph.aligned = true;
+  for (const auto& e : entries) ph.aligned &= gemm_aligned<float, kBM, kBN, false>(e);
+  std::vector<int> st = gemm_starts(entries, &ph.total);
+  ph.entries_off = append(entries.data(), entries.size());
+  ph.start_off = append(st.data(), st.size());
+  if (ph.total > 0) phases_.push_back(ph);
+}
+
+void LaunchList::add_ew(const std::vector<EwEntry>& entries) {
+  if (entries.empty()) return;
+  Phase ph{};
+  ph.kind = PH_EW;
+  ph.count = (int)entries.size();
+  ph.aligned = false;
+  std::vector<int> st(entries.size() + 1, 0);
+  for (size_t i = 0; i < entries.size(); ++i)
+    st[i + 1] = st[i] + (int)ceil_div((int64_t)entries[i].rows * entries[i].cols, kEwChunk);
+  ph.total = st.back();
+  ph.entries_off = append(entries.data(), entries.size());
+  ph.start_off = append(st.data(), st.size());
+  if (ph.total > 0) phases_.push_back(ph);
+}
+
+hipError_t LaunchList::run(const void* dev, hipStream_t s) const {
+  const char* base = static_cast<const char*>(dev);
+  for (const Phase& ph : phases_) {
+    const int* st = reinterpret_cast<const int*>(base + ph.start_off);
+    dim3 grid((unsigned)ph.total);
+    if (ph.kind == PH_GEMM_F64) {
+      const GemmP64* e = reinterpret_cast<const GemmP64*>(base + ph.entries_off);
+      if (ph.aligned)
+        gemm_grouped_kernel<double, double, double, float, kBM, kBN, 2, 2, false, true>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+      else
+        gemm_grouped_kernel<double, double, double, float, kBM, kBN, 2, 2, false, false>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else if (ph.kind == PH_GEMM_F32) {
+      const GemmP32* e = reinterpret_cast<const GemmP32*>(base + ph.entries_off);
+      if (ph.aligned)
+        gemm_grouped_kernel<float, float, float, float, kBM, kBN, 2, 2, false, true>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+      else
+        gemm_grouped_kernel<float, float, float, float, kBM, kBN, 2, 2, false, false>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else {
+      const EwEntry* e = reinterpret_cast<const EwEntry*>(base + ph.entries_off);
+      grouped_ew_kernel<<<grid, 256, 0, s>>>(e, st, ph.count);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items, int64_t n0) {
+  int64_t max_m = 0;
+  for (const auto& it : items) max_m = std::max(max_m, ceil_div(it.n, n0));
+  for (int64_t i = 0; i < max_m; ++i) {
+    std::vector<GemmParams<T, T, T, float>> trmm, upd;
+    for (const auto& it : items) {
+      const int64_t m = ceil_div(it.n, n0);
+      if (i >= m || it.k == 0) continue;
+      const int64_t r0 = i * n0, sz = std::min(n0, it.n - r0);
+      // X(S_i) = Linv_ii * B'(S_i)
+      auto p = gemm_params<T, T, T, float>();
+      p.A = it.Linv + i * n0 * n0; p.lda = n0;
+      p.B = (i == 0) ? it.B : it.R + r0 * it.ldr;
+      p.ldb = (i == 0) ? it.ldb : it.ldr;
+      p.Cout = it.X + r0 * it.ldx; p.ldco = it.ldx;
+      p.M = (int)sz; p.N = (int)it.k; p.K = (int)sz;
+      p.flags = G_A_LOWER;
+      trmm.push_back(p);
+      if (i + 1 < m) {
+        // B'(T_{i+1}) = B'(T_{i+1}) - L(T_{i+1}, S_i) X(S_i)
+        const int64_t t0 = r0 + n0;
+        auto q = gemm_params<T, T, T, float>();
+        q.A = it.L + t0 * it.ldl + r0; q.lda = it.ldl;
+        q.B = it.X + r0 * it.ldx; q.ldb = it.ldx;
+        q.Cin = (i == 0) ? it.B + t0 * it.ldb : it.R + t0 * it.ldr;
+        q.ldci = (i == 0) ? it.ldb : it.ldr;
+        q.Cout = it.R + t0 * it.ldr; q.ldco = it.ldr;
+        q.M = (int)(it.n - t0); q.N = (int)it.k; q.K = (int)sz;
+        q.alpha = -1.0; q.beta = 1.0;
+        q.flags = G_BETA;
+        upd.push_back(q);
+      }
+    }
+    if constexpr (std::is_same<T, double>::value) {
+      list.add_gemm64(trmm);
+      list.add_gemm64(upd);
+    } else {
+      list.add_gemm32(trmm);
+      list.add_gemm32(upd);
+    }
+  }
+}
+
+template void record_sweep<double>(LaunchList&, const std::vector<SweepItem<double>>&, int64_t);
+template void record_sweep<float>(LaunchList&, const std::vector<SweepItem<float>>&, int64_t);
+
+}  // namespace trsm
+
+// ---------------------------------------------------------------------------
+// C ABI: batches
+// ---------------------------------------------------------------------------
+using namespace trsm;
+
+struct trsm_batch_s {
+  std::vector<trsm_batch_item> items;
+  trsm_precision prec = TRSM_F64;
+  int64_t n0 = 128;
+  size_t table_bytes = 0;      // upper bound, reserved at the head of the workspace
+  size_t ws_bytes = 0;
+  std::vector<size_t> r_off;   // offset of each item's running right-hand side
+  LaunchList list;
+  void* pinned = nullptr;      // host staging of the table (page-locked)
+  size_t pinned_bytes = 0;
+  // captured graph, valid for (graph_ws, graph_stream)
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* graph_ws = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlignB = 256;
+inline size_t alignb(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
+
+bool is_pow2_64(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t linv32_offset(int64_t n, int64_t n0) {
+  const int64_t m = ceil_div(n, n0);
+  return alignb((size_t)m * n0 * n0 * 8);
+}
+
+template <typename T>
+void build_list(trsm_batch_s* b, char* ws) {
+  std::vector<SweepItem<T>> its;
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const trsm_batch_item& x = b->items[i];
+    SweepItem<T> s{};
+    s.n = x.n;
+    s.k = x.k;
+    s.L = static_cast<const T*>(x.L);
+    s.ldl = x.ldl;
+    const char* lb = static_cast<const char*>(x.Linv);
+    s.Linv = reinterpret_cast<const T*>(
+        lb + (std::is_same<T, float>::value ? linv32_offset(x.n, b->n0) : 0));
+    s.B = static_cast<const T*>(x.B);
+    s.ldb = x.ldb;
+    s.X = static_cast<T*>(x.X);
+    s.ldx = x.ldx;
+    s.R = reinterpret_cast<T*>(ws + b->r_off[i]);
+    s.ldr = std::max<int64_t>(x.k, 1);
+    its.push_back(s);
+  }
+  b->list.clear();
+  record_sweep<T>(b->list, its, b->n0);
+}
+
+}  // namespace
+
+extern "C" {
+
+trsm_status trsm_batch_create(int32_t count, const trsm_batch_item* items, trsm_precision prec,
+                              int64_t n0, trsm_batch_t* out) {
+  if (!out) return TRSM_EINVAL;
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !items)) return TRSM_EINVAL;
+  if (prec != TRSM_F64 && prec != TRSM_F32) return TRSM_EINVAL;
+  if (!is_pow2_64(n0)) return TRSM_EINVAL;
+  const size_t es = prec == TRSM_F32 ? 4 : 8;
+  for (int32_t i = 0; i < count; ++i) {
+    const trsm_batch_item& x = items[i];
+    if (x.n < 0 || x.k < 0 || x.n > (1 << 30) || x.k > (1 << 30)) return TRSM_EINVAL;
+    if (x.n == 0 || x.k == 0) continue;
+    if (!x.L || !x.Linv || !x.B || !x.X) return TRSM_EINVAL;
+    if (x.ldl < x.n || x.ldb < x.k || x.ldx < x.k) return TRSM_EINVAL;
+    if (((uintptr_t)x.Linv) % kAlignB) return TRSM_EINVAL;
+    // X must not overlap B (the batch has no in-place path)
+    const uintptr_t b0 = (uintptr_t)x.B, b1 = b0 + ((size_t)(x.n - 1) * x.ldb + x.k) * es;
+    const uintptr_t x0 = (uintptr_t)x.X, x1 = x0 + ((size_t)(x.n - 1) * x.ldx + x.k) * es;
+    if (b0 < x1 && x0 < b1) return TRSM_EINVAL;
+  }
+  trsm_batch_s* b = new (std::nothrow) trsm_batch_s();
+  if (!b) return TRSM_ENOMEM;
+  b->items.assign(items, items + count);
+  b->prec = prec;
+  b->n0 = n0;
+  // table size: record once with a null workspace to measure it
+  size_t off = 0;
+  b->r_off.resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    b->r_off[i] = off;
+    off = alignb(off + (size_t)items[i].n * std::max<int64_t>(items[i].k, 1) * es);
+  }
+  if (prec == TRSM_F64) build_list<double>(b, nullptr);
+  else build_list<float>(b, nullptr);
+  b->table_bytes = alignb(b->list.table_bytes() + 64);
+  for (int32_t i = 0; i < count; ++i) b->r_off[i] += b->table_bytes;
+  b->ws_bytes = b->table_bytes + off;
+  *out = b;
+  return TRSM_OK;
+}
+
+trsm_status trsm_batch_workspace_bytes(trsm_batch_t b, size_t* bytes) {
+  if (!b || !bytes) return TRSM_EINVAL;
+  *bytes = b->ws_bytes;
+  return TRSM_OK;
+}
+
+trsm_status trsm_batch_run(trsm_batch_t b, void* workspace, void* stream, int32_t use_graph) {
+  if (!b) return TRSM_EINVAL;
+  if (b->items.empty()) return TRSM_OK;
+  if (!workspace || ((uintptr_t)workspace) % kAlignB) return TRSM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (use_graph && b->exec && b->graph_ws == workspace && b->graph_stream == s) {
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    return e == hipSuccess ? TRSM_OK : TRSM_EHIP;
+  }
+  char* ws = static_cast<char*>(workspace);
+  if (b->prec == TRSM_F64) build_list<double>(b, ws);
+  else build_list<float>(b, ws);
+  const size_t tb = b->list.table_bytes();
+  if (tb > b->table_bytes) return TRSM_EINVAL;  // cannot happen: same recording
+  if (b->pinned_bytes < tb) {
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    b->pinned = nullptr;
+    b->pinned_bytes = 0;
+    if (hipHostMalloc(&b->pinned, tb, hipHostMallocDefault) != hipSuccess) return TRSM_ENOMEM;
+    b->pinned_bytes = tb;
+  }
+  memcpy(b->pinned, b->list.host_table(), tb);
+  if (!use_graph) {
+    if (hipMemcpyAsync(ws, b->pinned, tb, hipMemcpyHostToDevice, s) != hipSuccess) return TRSM_EHIP;
+    return b->list.run(ws, s) == hipSuccess ? TRSM_OK : TRSM_EHIP;
+  }
+  // capture the table upload and every launch into one graph
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TRSM_EHIP;
+  hipError_t e1 = hipMemcpyAsync(ws, b->pinned, tb, hipMemcpyHostToDevice, s);
+  hipError_t e2 = e1 == hipSuccess ? b->list.run(ws, s) : e1;
+  hipGraph_t g = nullptr;
+  hipError_t e3 = hipStreamEndCapture(s, &g);
+  if (e2 != hipSuccess || e3 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return TRSM_EHIP;
+  }
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    b->exec = nullptr;
+    return TRSM_EHIP;
+  }
+  b->graph = g;
+  b->graph_ws = workspace;
+  b->graph_stream = s;
+  return hipGraphLaunch(b->exec, s) == hipSuccess ? TRSM_OK : TRSM_EHIP;
+}
+
+trsm_status trsm_batch_destroy(trsm_batch_t b) {
+  if (!b) return TRSM_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  delete b;
+  return TRSM_OK;
+}
+
+}  // extern "C"

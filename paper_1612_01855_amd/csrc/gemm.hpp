@@ -31,6 +31,8 @@
 
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace trsm {
 
 enum GemmFlags : uint32_t {
@@ -76,11 +78,13 @@ __device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
+// One BM x BN output tile of one batch entry.  `bid` is the tile's index
+// among the nwg tiles of the entry; `z` the batch index.
 template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
           int GROUP_M = 8, bool XCD_REMAP = false>
-__global__ __launch_bounds__(WGM * WGN * 64, 2)
-void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
+__device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
+                                          int bid, int nwg) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
   using Out = typename MF::Out;
@@ -114,7 +118,6 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   const int gi = lane & 15, g = lane >> 4;
 
   // ---- batch offsets --------------------------------------------------
-  const int z = blockIdx.z;
   const int zo = z / p.zdiv, zi = z % p.zdiv;
   const TIn* __restrict__ A = p.A + zo * p.sa_o + zi * p.sa_i;
   const TIn* __restrict__ B = p.B + zo * p.sb_o + zi * p.sb_i;
@@ -123,8 +126,6 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
 
   // ---- tile coordinates (XCD-aware, grouped) -----------------------------
   const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
-  int bid = blockIdx.x;
-  const int nwg = gridDim.x;
   if (XCD_REMAP && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
   const int per_group = GROUP_M * ntn;
   const int grp = bid / per_group;
@@ -295,31 +296,78 @@ void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
   const bool use_beta = (p.flags & G_BETA) && Ci;
   const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
   const bool c2t = p.flags & G_C2_T;
-  const Acc alpha = static_cast<Acc>(p.alpha);
-  const Acc beta = static_cast<Acc>(p.beta);
+  // the epilogue runs in binary64 whenever C is binary64 on either side
+  using Epi = typename std::conditional<std::is_same<TCout, double>::value ||
+                                            std::is_same<TCin, double>::value,
+                                        double, Acc>::type;
+  const Epi alpha = static_cast<Epi>(p.alpha);
+  const Epi beta = static_cast<Epi>(p.beta);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = r0 + wm * WTM + i * 16 + MF::out_row(g, r);
       if (row >= M) continue;
-      Acc rs = Acc(1);
-      if (use_rs) rs = static_cast<Acc>(p.rscale[(int64_t)row * p.ld_rs]);
+      Epi rs = Epi(1);
+      if (use_rs) rs = static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = c0 + wn * WTN + j * 16 + gi;
         if (col >= N) continue;
-        Acc v = alpha * (acc[i][j][r] * rs);
-        if (use_beta) v += beta * static_cast<Acc>(Ci[(int64_t)row * p.ldci + col]);
+        Epi v = alpha * (static_cast<Epi>(acc[i][j][r]) * rs);
+        if (use_beta) v += beta * static_cast<Epi>(Ci[(int64_t)row * p.ldci + col]);
         Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
         if (p.C2) {
-          const TC2 w = cvt<TC2>(v * static_cast<Acc>(p.c2scale));
+          const TC2 w = cvt<TC2>(v * static_cast<Epi>(p.c2scale));
           if (c2t) p.C2[(int64_t)col * p.ldc2 + row] = w;
           else p.C2[(int64_t)row * p.ldc2 + col] = w;
         }
       }
     }
   }
+}
+
+template <typename TIn, typename TCin, typename TCout, typename TC2,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+__global__ __launch_bounds__(WGM * WGN * 64, 2)
+void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, blockIdx.z, blockIdx.x,
+                                                                      gridDim.x);
+}
+
+// Grouped launch: many independent products of one element type in one
+// grid.  Entry e owns workgroups [tile_start[e], tile_start[e+1]); within an
+// entry the workgroups cover batch x tiles as in gemm_kernel.
+template <typename TIn, typename TCin, typename TCout, typename TC2,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+__global__ __launch_bounds__(WGM * WGN * 64, 2)
+void gemm_grouped_kernel(const GemmParams<TIn, TCin, TCout, TC2>* __restrict__ entries,
+                         const int* __restrict__ tile_start, int nentries) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nentries - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmParams<TIn, TCin, TCout, TC2>& p = entries[lo];
+  const int tiles = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
+  const int local = b - tile_start[lo];
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, local / tiles,
+                                                                      local % tiles, tiles);
+}
+
+// Whether the 16-byte vector path may be used for a product.
+template <typename TIn, int BM, int BN, bool BKMAJOR, typename P>
+inline bool gemm_aligned(const P& p) {
+  constexpr int VEC = 16 / sizeof(TIn);
+  constexpr int BK = 128 / sizeof(TIn);
+  auto al = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
+  const int64_t span_a = (int64_t)BM * p.lda * (int64_t)sizeof(TIn);
+  const int64_t span_b = (int64_t)(BKMAJOR ? BN : BK) * p.ldb * (int64_t)sizeof(TIn);
+  return al(p.A) && al(p.B) && p.lda % VEC == 0 && p.ldb % VEC == 0 && p.sa_o % VEC == 0 &&
+         p.sa_i % VEC == 0 && p.sb_o % VEC == 0 && p.sb_i % VEC == 0 && p.K % VEC == 0 &&
+         (BKMAJOR || p.N % VEC == 0) && span_a < kBufOOB && span_b < kBufOOB;
 }
 
 // Host-side launch helper.  Picks the aligned (16-byte vector) path when every
@@ -329,15 +377,7 @@ template <typename TIn, typename TCin, typename TCout, typename TC2,
 inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int batch,
                               hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
-  constexpr int VEC = 16 / sizeof(TIn);
-  auto al = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
-  constexpr int BK = 128 / sizeof(TIn);
-  const int64_t span_a = (int64_t)BM * p.lda * (int64_t)sizeof(TIn);
-  const int64_t span_b = (int64_t)(BKMAJOR ? BN : BK) * p.ldb * (int64_t)sizeof(TIn);
-  const bool aligned = al(p.A) && al(p.B) && p.lda % VEC == 0 && p.ldb % VEC == 0 &&
-                       p.sa_o % VEC == 0 && p.sa_i % VEC == 0 && p.sb_o % VEC == 0 &&
-                       p.sb_i % VEC == 0 && p.K % VEC == 0 && (BKMAJOR || p.N % VEC == 0) &&
-                       span_a < kBufOOB && span_b < kBufOOB;
+  const bool aligned = gemm_aligned<TIn, BM, BN, BKMAJOR>(p);
   const int64_t tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
   dim3 grid((unsigned)tiles, 1, (unsigned)batch);
   dim3 block(WGM * WGN * 64);

@@ -45,10 +45,33 @@ class Info(ctypes.Structure):
                 ("unrefined_error", ctypes.c_double)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int64), ("L", ctypes.c_void_p),
+                ("ldl", ctypes.c_int64), ("Linv", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("ldb", ctypes.c_int64), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("flops_done", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("hbm_budget", ctypes.c_size_t),
+                ("hbm_in_use", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t),
+                ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("max_in_flight", ctypes.c_int32), ("factors", ctypes.c_int32)]
+
+
+# trsm_req_state
+REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_UNKNOWN = range(5)
+
 EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
            "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
-           "trsm_plan_timing"]
+           "trsm_plan_timing", "trsm_batch_create", "trsm_batch_workspace_bytes",
+           "trsm_batch_run", "trsm_batch_destroy", "trsm_server_create",
+           "trsm_server_register_L", "trsm_serve_submit", "trsm_serve_poll",
+           "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy"]
 
 
 class TrsmError(RuntimeError):
@@ -90,6 +113,31 @@ def _load():
     lib.trsm_plan_timing.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.trsm_plan_timing.restype = i32
+    lib.trsm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(BatchItem), i32, i64,
+                                      ctypes.POINTER(vp)]
+    lib.trsm_batch_create.restype = i32
+    lib.trsm_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.trsm_batch_workspace_bytes.restype = i32
+    lib.trsm_batch_run.argtypes = [vp, vp, vp, ctypes.c_int32]
+    lib.trsm_batch_run.restype = i32
+    lib.trsm_batch_destroy.argtypes = [vp]
+    lib.trsm_batch_destroy.restype = i32
+    lib.trsm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, i64, ctypes.POINTER(vp)]
+    lib.trsm_server_create.restype = i32
+    lib.trsm_server_register_L.argtypes = [vp, vp, i64, i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.trsm_server_register_L.restype = i32
+    lib.trsm_serve_submit.argtypes = [vp, ctypes.c_int32, vp, i64, i64, vp, i64,
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.trsm_serve_submit.restype = i32
+    lib.trsm_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.trsm_serve_poll.restype = i32
+    lib.trsm_server_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    lib.trsm_server_stats.restype = i32
+    lib.trsm_server_reset_stats.argtypes = [vp]
+    lib.trsm_server_reset_stats.restype = i32
+    lib.trsm_server_destroy.argtypes = [vp]
+    lib.trsm_server_destroy.restype = i32
     return lib
 
 
@@ -166,6 +214,70 @@ def trsm_plan_timing(plan: int):
     _check(_lib.trsm_plan_timing(plan, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)),
            "trsm_plan_timing")
     return n.value, ms.value, fl.value
+
+
+def trsm_batch_create(items, precision: int = F64, n0: int = 128) -> int:
+    arr = (BatchItem * max(len(items), 1))(*items)
+    h = ctypes.c_void_p()
+    _check(_lib.trsm_batch_create(len(items), arr, precision, n0, ctypes.byref(h)),
+           "trsm_batch_create")
+    return h.value
+
+
+def trsm_batch_workspace_bytes(batch: int) -> int:
+    v = ctypes.c_size_t()
+    _check(_lib.trsm_batch_workspace_bytes(batch, ctypes.byref(v)), "trsm_batch_workspace_bytes")
+    return v.value
+
+
+def trsm_batch_run(batch: int, workspace: int, stream: int = 0, use_graph: bool = False) -> None:
+    _check(_lib.trsm_batch_run(batch, workspace, stream, 1 if use_graph else 0), "trsm_batch_run")
+
+
+def trsm_batch_destroy(batch: int) -> None:
+    _check(_lib.trsm_batch_destroy(batch), "trsm_batch_destroy")
+
+
+def trsm_server_create(hbm_budget: int, max_slots: int = 64, n0: int = 128) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.trsm_server_create(hbm_budget, max_slots, n0, ctypes.byref(h)),
+           "trsm_server_create")
+    return h.value
+
+
+def trsm_server_register_L(srv: int, L: int, n: int, ldl: int) -> int:
+    lid = ctypes.c_int32()
+    _check(_lib.trsm_server_register_L(srv, L, n, ldl, ctypes.byref(lid)),
+           "trsm_server_register_L")
+    return lid.value
+
+
+def trsm_serve_submit(srv: int, l_id: int, B: int, k: int, ldb: int, X: int, ldx: int) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.trsm_serve_submit(srv, l_id, B, k, ldb, X, ldx, ctypes.byref(t)),
+           "trsm_serve_submit")
+    return t.value
+
+
+def trsm_serve_poll(srv: int, ticket: int):
+    """(state, status, latency_us); a finished ticket is reported once."""
+    st, lat = ctypes.c_int(), ctypes.c_double()
+    status = _lib.trsm_serve_poll(srv, ticket, ctypes.byref(st), ctypes.byref(lat))
+    return st.value, status, lat.value
+
+
+def trsm_server_stats(srv: int) -> ServeStats:
+    st = ServeStats()
+    _check(_lib.trsm_server_stats(srv, ctypes.byref(st)), "trsm_server_stats")
+    return st
+
+
+def trsm_server_reset_stats(srv: int) -> None:
+    _check(_lib.trsm_server_reset_stats(srv), "trsm_server_reset_stats")
+
+
+def trsm_server_destroy(srv: int) -> None:
+    _check(_lib.trsm_server_destroy(srv), "trsm_server_destroy")
 
 
 # ---- torch-tensor convenience (memory ownership only) ------------------------

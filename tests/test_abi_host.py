@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "trsm.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(trsm_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(trsm_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -131,3 +131,40 @@ def test_residual_validation_without_gpu(T):
     assert lib.trsm_residual(4, 4, fake, 3, fake + 4096, 4, fake + 8192, 4, fake + 16384, 4,
                              fake, norms, None) == T.EINVAL   # ldl < n
     assert lib.trsm_residual(0, 4, None, 0, None, 4, None, 4, None, 4, None, norms, None) == T.OK
+
+
+def test_batch_create_validation_and_workspace(T):
+    fake = 1 << 24
+    good = T.BatchItem(300, 7, fake, 300, fake, fake + (1 << 22), 7, fake + (1 << 23), 7)
+    b = T.trsm_batch_create([good], T.F64, 128)
+    try:
+        ws = T.trsm_batch_workspace_bytes(b)
+        assert ws >= 300 * 7 * 8          # running right-hand side
+    finally:
+        T.trsm_batch_destroy(b)
+    bad_ld = T.BatchItem(300, 7, fake, 299, fake, fake + (1 << 22), 7, fake + (1 << 23), 7)
+    overlap = T.BatchItem(300, 7, fake, 300, fake, fake + (1 << 22), 7, fake + (1 << 22) + 8, 7)
+    misaligned = T.BatchItem(300, 7, fake, 300, fake + 8, fake + (1 << 22), 7, fake + (1 << 23), 7)
+    for item in (bad_ld, overlap, misaligned):
+        with pytest.raises(T.TrsmError) as e:
+            T.trsm_batch_create([item], T.F64, 128)
+        assert e.value.status == T.EINVAL
+    with pytest.raises(T.TrsmError):
+        T.trsm_batch_create([good], T.MIXED_BF16, 128)   # plain precisions only
+    with pytest.raises(T.TrsmError):
+        T.trsm_batch_create([good], T.F64, 96)            # n0 must be a power of two
+    empty = T.trsm_batch_create([], T.F32, 64)
+    T.trsm_batch_run(empty, 0, 0, False)                  # nothing to do: no device work
+    T.trsm_batch_destroy(empty)
+
+
+def test_server_argument_validation_without_gpu(T):
+    lib = T._lib
+    h = ctypes.c_void_p()
+    assert lib.trsm_server_create(1 << 30, 0, 128, ctypes.byref(h)) == T.EINVAL   # no slots
+    assert lib.trsm_server_create(1 << 30, 8, 96, ctypes.byref(h)) == T.EINVAL    # n0
+    assert lib.trsm_server_create(1 << 10, 8, 128, ctypes.byref(h)) == T.EINVAL   # tiny budget
+    assert lib.trsm_server_create(1 << 30, 8, 128, None) == T.EINVAL
+    st = ctypes.c_int()
+    assert lib.trsm_serve_poll(None, 1, ctypes.byref(st), None) == T.EINVAL
+    assert lib.trsm_server_destroy(None) == T.OK

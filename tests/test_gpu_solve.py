@@ -281,3 +281,80 @@ def test_residual_entry_point(torch, T):
     assert abs(norms[0] - oracle.fro(Rref)) <= 1e-15 * scale
     assert abs(norms[1] - oracle.fro(X)) <= 1e-14 * oracle.fro(X)
     assert abs(norms[2] - np.abs(Rref).max()) <= 1e-15 * scale
+
+
+# ---- batches (grouped launches, optional hipGraph replay) -------------------------
+
+def _batch_setup(torch, T, shapes, prec, n0, seed):
+    dt = torch.float32 if prec == "f32" else torch.float64
+    sysd = []
+    for i, (n, k) in enumerate(shapes):
+        L, B = gen.easy_system(n, k, seed + i, upper=np.nan)
+        Ld, Bd = dev(torch, L, dt), dev(torch, B, dt)
+        s = T.Solver.create(n, k, prec, n0)
+        s.invert(Ld)
+        Xd = torch.full_like(Bd, float("nan"))
+        sysd.append(dict(L=L, B=B, Ld=Ld, Bd=Bd, Xd=Xd, s=s))
+    torch.cuda.synchronize()
+    items = [T.BatchItem(d["Bd"].shape[0], d["Bd"].shape[1], d["Ld"].data_ptr(), d["Ld"].shape[0],
+                         d["s"].linv_ptr, d["Bd"].data_ptr(), d["Bd"].shape[1],
+                         d["Xd"].data_ptr(), d["Xd"].shape[1]) for d in sysd]
+    return sysd, items
+
+
+def _run_batch(torch, T, items, prec, n0, use_graph=False, replays=1):
+    b = T.trsm_batch_create(items, T.PRECISIONS[prec], n0)
+    ws = torch.empty(T.trsm_batch_workspace_bytes(b) + 256, dtype=torch.uint8, device="cuda")
+    wsp = (ws.data_ptr() + 255) // 256 * 256
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(replays):
+        T.trsm_batch_run(b, wsp, stream, use_graph)
+        torch.cuda.synchronize()
+    return b, ws, wsp
+
+
+SHAPES = [(300, 7), (1000, 64), (64, 1), (513, 130), (128, 128), (2000, 33)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_matches_oracle_and_is_mix_independent(torch, T, prec):
+    n0 = 128
+    sysd, items = _batch_setup(torch, T, SHAPES, prec, n0, 70)
+    b, ws, _ = _run_batch(torch, T, items, prec, n0)
+    mixed = [host(d["Xd"]).copy() for d in sysd]
+    T.trsm_batch_destroy(b)
+    for d, X in zip(sysd, mixed):
+        if prec == "f32":
+            Lr = d["L"].astype(np.float32).astype(np.float64)
+            Br = d["B"].astype(np.float32).astype(np.float64)
+            tol = TOL32
+        else:
+            Lr, Br, tol = d["L"], d["B"], TOL64
+        assert oracle.rel_fro_err(X, oracle.trsm(Lr, Br)) <= tol
+    # each system alone in a batch of one gives the same bits as in the mix
+    for d, item, X in zip(sysd, items, mixed):
+        d["Xd"].fill_(float("nan"))
+        b1, ws1, _ = _run_batch(torch, T, [item], prec, n0)
+        T.trsm_batch_destroy(b1)
+        assert np.array_equal(host(d["Xd"]), X)
+    for d in sysd:
+        d["s"].close()
+
+
+def test_batch_graph_replays_match_eager(torch, T):
+    n0 = 128
+    sysd, items = _batch_setup(torch, T, SHAPES[:4], "f64", n0, 90)
+    b, ws, wsp = _run_batch(torch, T, items, "f64", n0)
+    eager = [host(d["Xd"]).copy() for d in sysd]
+    stream = torch.cuda.current_stream().cuda_stream
+    for rep in range(4):
+        for d in sysd:
+            d["Xd"].fill_(float("nan"))       # eager work between replays
+        torch.cuda.synchronize()
+        T.trsm_batch_run(b, wsp, stream, True)
+        torch.cuda.synchronize()
+        for d, X in zip(sysd, eager):
+            assert np.array_equal(host(d["Xd"]), X), rep
+    T.trsm_batch_destroy(b)
+    for d in sysd:
+        d["s"].close()
