@@ -74,6 +74,124 @@ def cpu_baseline(L, B, seconds_hint: float = 15.0):
                       f"(columns are independent), binary64 forward substitution"}
 
 
+def serving_bench(args, torch, T, gen, dev):
+    """Continuous-batching serving: resident factors with cached inverted
+    blocks, Poisson arrivals of binary64 solves (binary32 sweeps + one binary64
+    refinement step).  Reports saturation throughput and p50/p99 latency at a
+    fixed arrival rate."""
+    import math
+    import numpy as np
+    nf = args.serve_factors
+    sizes = gen.serving_factor_sizes(nf, args.seed + 11)
+    n0 = 512
+    resident = 0
+    for n in sizes:
+        n0f = min(n0, 1 << (int(n) - 1).bit_length())
+        m = -(-int(n) // n0f)
+        resident += 12 * int(n) * (int(n) + 4) + 12 * m * n0f * n0f + 4096
+    budget = resident + (6 << 30)
+    srv = T.trsm_server_create(budget, 512, n0)
+    try:
+        t0 = time.perf_counter()
+        lids = []
+        for i, n in enumerate(sizes):
+            n = int(n)
+            g = torch.Generator(device=dev).manual_seed(args.seed * 7919 + i)
+            L = torch.rand((n, n), generator=g, device=dev, dtype=torch.float64)
+            L.mul_(2.0).sub_(1.0).mul_(1.0 / n)
+            L = torch.tril(L, -1)
+            L.diagonal().copy_(torch.rand(n, generator=g, device=dev, dtype=torch.float64) + 1.0)
+            torch.cuda.synchronize()
+            lids.append(T.trsm_server_register_L(srv, L.data_ptr(), n, n))
+            del L
+        log(f"serving: registered {nf} factors (n in [{int(sizes.min())}, {int(sizes.max())}]) "
+            f"in {time.perf_counter() - t0:.1f} s; resident {resident / 2**30:.2f} GiB")
+
+        def make_requests(stream):
+            bufs = []
+            g = torch.Generator(device=dev).manual_seed(args.seed * 104729 + len(stream))
+            for r in stream:
+                n = int(sizes[r.factor])
+                B = torch.randn((n, r.k), generator=g, device=dev, dtype=torch.float64)
+                bufs.append((r, n, B, torch.empty_like(B)))
+            torch.cuda.synchronize()
+            return bufs
+
+        def drive(bufs, timed_arrivals):
+            outstanding = {}
+            lat = []
+            i = 0
+            t_start = time.perf_counter()
+            flops = 0.0
+            while i < len(bufs) or outstanding:
+                now = time.perf_counter() - t_start
+                while i < len(bufs) and (not timed_arrivals or bufs[i][0].t_arrival <= now):
+                    r, n, B, X = bufs[i]
+                    t = T.trsm_serve_submit(srv, lids[r.factor], B.data_ptr(), r.k, r.k,
+                                            X.data_ptr(), r.k)
+                    outstanding[t] = (n, r.k)
+                    i += 1
+                for t in list(outstanding):
+                    st, status, l_us = T.trsm_serve_poll(srv, t)
+                    if st == T.REQ_DONE:
+                        n, k = outstanding.pop(t)
+                        lat.append(l_us)
+                        flops += float(n) * n * k
+                    elif st == T.REQ_ERROR:
+                        raise RuntimeError(f"serving request failed: {T.status_string(status)}")
+                if i < len(bufs) and timed_arrivals:
+                    wait = bufs[i][0].t_arrival - (time.perf_counter() - t_start)
+                    if wait > 0:
+                        time.sleep(min(wait, 2e-4))
+                elif outstanding:
+                    time.sleep(5e-5)
+            return time.perf_counter() - t_start, lat, flops
+
+        # saturation: everything submitted at once
+        sat = gen.request_stream(min(1000, args.serve_requests), 1.0, nf, args.seed + 21)
+        bufs = make_requests(sat)
+        drive(bufs[:50], False)                       # warm the kernels
+        T.trsm_server_reset_stats(srv)
+        wall, lat, flops = drive(bufs, False)
+        sat_rps = len(bufs) / wall
+        log(f"serving: saturation {sat_rps:.0f} requests/s, {flops / wall / 1e12:.2f} TFLOP/s")
+        del bufs
+        # Poisson streams at fixed fractions of the saturation rate
+        sweep = []
+        headline = None
+        for load in sorted(set([0.25, args.serve_load, 0.75])):
+            rate = load * sat_rps
+            stream = gen.request_stream(args.serve_requests, rate, nf, args.seed + 31)
+            bufs = make_requests(stream)
+            T.trsm_server_reset_stats(srv)
+            wall, lat, flops = drive(bufs, True)
+            st = T.trsm_server_stats(srv)
+            lat = np.sort(np.array(lat))
+            p50 = float(lat[max(0, math.ceil(0.5 * len(lat)) - 1)])
+            p99 = float(lat[max(0, math.ceil(0.99 * len(lat)) - 1)])
+            log(f"serving: {len(lat)} requests at {rate:.0f}/s (load {load}): p50 {p50:.0f} us, "
+                f"p99 {p99:.0f} us, {flops / wall / 1e12:.2f} TFLOP/s, {st.batches} batches, "
+                f"max in flight {st.max_in_flight}")
+            rec = {"load_fraction": load, "rate_hz": round(rate, 1), "requests": len(lat),
+                   "p50_us": round(p50, 1), "p99_us": round(p99, 1),
+                   "mean_us": round(float(lat.mean()), 1),
+                   "tflops_n2k": round(flops / wall / 1e12, 4), "batches": int(st.batches),
+                   "max_in_flight": int(st.max_in_flight)}
+            sweep.append(rec)
+            if load == args.serve_load:
+                headline = rec
+            del bufs
+        out = {"factors": nf, "n_range": [int(sizes.min()), int(sizes.max())],
+               "k_range": [1, 512], "saturation_rps": round(sat_rps, 1),
+               "hbm_budget_gib": round(budget / 2**30, 2), "n0_max": n0,
+               "precision": "binary64 in/out; binary32 sweeps + one binary64 refinement step"}
+        out.update(headline)
+        out["rate_sweep"] = sweep
+        return out
+    finally:
+        T.trsm_server_destroy(srv)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +204,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-factors", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="Poisson arrival rate as a fraction of the measured saturation rate")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device 3 times (reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -215,6 +338,13 @@ def main():
             except Exception as e:  # report, never hide
                 mixed[prec] = {"error": str(e)}
 
+    serving = None
+    if not args.no_serving and args.precision == "f64":
+        del Xd
+        torch.cuda.empty_cache()
+        Xd = None
+        serving = serving_bench(args, torch, T, gen, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a column sample")
@@ -242,6 +372,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "serving": serving,
         "check": check,
     }
     print(json.dumps(out), flush=True)

@@ -192,7 +192,8 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl,
  *  use_graph != 0 the table upload and all launches are captured into a
  *  hipGraph on the first call and replayed by later calls that pass the same
  *  workspace and stream (the items' buffers must then be unchanged
- *  addresses; their contents may change).
+ *  addresses; their contents may change).  Capture needs a created stream:
+ *  use_graph with the NULL stream is TRSM_EINVAL.
  * trsm_batch_destroy releases the handle (and its graph).
  */
 typedef struct trsm_batch_item {

@@ -162,12 +162,13 @@ hipError_t LaunchList::run(const void* dev, hipStream_t s) const {
 }
 
 template <typename T>
-void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items, int64_t n0) {
+void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items) {
   int64_t max_m = 0;
-  for (const auto& it : items) max_m = std::max(max_m, ceil_div(it.n, n0));
+  for (const auto& it : items) max_m = std::max(max_m, ceil_div(it.n, it.n0));
   for (int64_t i = 0; i < max_m; ++i) {
     std::vector<GemmParams<T, T, T, float>> trmm, upd;
     for (const auto& it : items) {
+      const int64_t n0 = it.n0;
       const int64_t m = ceil_div(it.n, n0);
       if (i >= m || it.k == 0) continue;
       const int64_t r0 = i * n0, sz = std::min(n0, it.n - r0);
@@ -205,8 +206,8 @@ void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items, int6
   }
 }
 
-template void record_sweep<double>(LaunchList&, const std::vector<SweepItem<double>>&, int64_t);
-template void record_sweep<float>(LaunchList&, const std::vector<SweepItem<float>>&, int64_t);
+template void record_sweep<double>(LaunchList&, const std::vector<SweepItem<double>>&);
+template void record_sweep<float>(LaunchList&, const std::vector<SweepItem<float>>&);
 
 }  // namespace trsm
 
@@ -252,11 +253,12 @@ void build_list(trsm_batch_s* b, char* ws) {
     SweepItem<T> s{};
     s.n = x.n;
     s.k = x.k;
+    s.n0 = effective_n0(x.n, b->n0);
     s.L = static_cast<const T*>(x.L);
     s.ldl = x.ldl;
     const char* lb = static_cast<const char*>(x.Linv);
     s.Linv = reinterpret_cast<const T*>(
-        lb + (std::is_same<T, float>::value ? linv32_offset(x.n, b->n0) : 0));
+        lb + (std::is_same<T, float>::value ? linv32_offset(x.n, s.n0) : 0));
     s.B = static_cast<const T*>(x.B);
     s.ldb = x.ldb;
     s.X = static_cast<T*>(x.X);
@@ -266,7 +268,7 @@ void build_list(trsm_batch_s* b, char* ws) {
     its.push_back(s);
   }
   b->list.clear();
-  record_sweep<T>(b->list, its, b->n0);
+  record_sweep<T>(b->list, its);
 }
 
 }  // namespace
@@ -325,9 +327,11 @@ trsm_status trsm_batch_run(trsm_batch_t b, void* workspace, void* stream, int32_
   if (b->items.empty()) return TRSM_OK;
   if (!workspace || ((uintptr_t)workspace) % kAlignB) return TRSM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (use_graph && !s) return TRSM_EINVAL;  // the legacy default stream cannot be captured
+  auto fail = [](hipError_t e) { return (trsm_status)note_hip_error(e); };
   if (use_graph && b->exec && b->graph_ws == workspace && b->graph_stream == s) {
     hipError_t e = hipGraphLaunch(b->exec, s);
-    return e == hipSuccess ? TRSM_OK : TRSM_EHIP;
+    return e == hipSuccess ? TRSM_OK : fail(e);
   }
   char* ws = static_cast<char*>(workspace);
   if (b->prec == TRSM_F64) build_list<double>(b, ws);
@@ -343,32 +347,36 @@ trsm_status trsm_batch_run(trsm_batch_t b, void* workspace, void* stream, int32_
   }
   memcpy(b->pinned, b->list.host_table(), tb);
   if (!use_graph) {
-    if (hipMemcpyAsync(ws, b->pinned, tb, hipMemcpyHostToDevice, s) != hipSuccess) return TRSM_EHIP;
-    return b->list.run(ws, s) == hipSuccess ? TRSM_OK : TRSM_EHIP;
+    hipError_t e = hipMemcpyAsync(ws, b->pinned, tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = b->list.run(ws, s);
+    return e == hipSuccess ? TRSM_OK : fail(e);
   }
   // capture the table upload and every launch into one graph
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TRSM_EHIP;
+  hipError_t e0 = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e0 != hipSuccess) return fail(e0);
   hipError_t e1 = hipMemcpyAsync(ws, b->pinned, tb, hipMemcpyHostToDevice, s);
   hipError_t e2 = e1 == hipSuccess ? b->list.run(ws, s) : e1;
   hipGraph_t g = nullptr;
   hipError_t e3 = hipStreamEndCapture(s, &g);
   if (e2 != hipSuccess || e3 != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
-    return TRSM_EHIP;
+    return fail(e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : hipErrorUnknown));
   }
-  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+  hipError_t e4 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e4 != hipSuccess) {
     (void)hipGraphDestroy(g);
     b->exec = nullptr;
-    return TRSM_EHIP;
+    return fail(e4);
   }
   b->graph = g;
   b->graph_ws = workspace;
   b->graph_stream = s;
-  return hipGraphLaunch(b->exec, s) == hipSuccess ? TRSM_OK : TRSM_EHIP;
+  hipError_t e5 = hipGraphLaunch(b->exec, s);
+  return e5 == hipSuccess ? TRSM_OK : fail(e5);
 }
 
 trsm_status trsm_batch_destroy(trsm_batch_t b) {

@@ -76,10 +76,11 @@ class LaunchList {
   std::vector<Phase> phases_;
 };
 
-// One system of a batch in working precision T.
+// One system of a batch in working precision T.  n0 is the system's own
+// diagonal block size (the plan caps it at the next power of two >= n).
 template <typename T>
 struct SweepItem {
-  int64_t n, k;
+  int64_t n, k, n0;
   const T* L; int64_t ldl;      // lower triangle read
   const T* Linv;                // m packed n0 x n0 inverses (element type T)
   const T* B; int64_t ldb;      // right-hand side (read)
@@ -87,8 +88,17 @@ struct SweepItem {
   T* R; int64_t ldr;            // running right-hand side (workspace, n x k)
 };
 
-// Append the 2m-1 phases of the right-looking sweep for all items (common n0).
+// Append the 2m-1 phases of the right-looking sweep for all items; phase i
+// of every item goes into the same grouped launch.
 template <typename T>
-void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items, int64_t n0);
+void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items);
+
+// The block size a plan made with (n, n0) uses: n0 capped at the next power
+// of two >= n.
+inline int64_t effective_n0(int64_t n, int64_t n0) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return n0 > p ? p : n0;
+}
 
 }  // namespace trsm

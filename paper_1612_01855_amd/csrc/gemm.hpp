@@ -22,11 +22,12 @@
 // chunks of BK with two LDS buffers and a register prefetch of the next
 // chunk, one barrier per chunk.  Tiles are visited in groups of GROUP_M row
 // tiles (column-major inside a group) so that concurrently running
-// workgroups share A and B panels in L2.  Workgroup ids are NOT regrouped
-// per XCD by default: the hardware deals consecutive ids to the XCDs in turn,
-// which spreads the uneven tile costs of a triangular product evenly over the
-// eight XCDs (giving each XCD a contiguous range of tiles made the
-// lower-triangular residual twice as slow).
+// workgroups share A and B panels in L2.  The hardware deals consecutive
+// workgroup ids to the eight XCDs in turn; dense products regroup the ids so
+// that each XCD works on a contiguous range of tiles (2.3x less L2-miss
+// traffic), triangular products keep the round-robin order because a
+// contiguous range per XCD unbalanced their uneven tile costs (the
+// lower-triangular residual ran twice as slow).
 #pragma once
 
 #include "common.hpp"
@@ -126,7 +127,12 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
 
   // ---- tile coordinates (XCD-aware, grouped) -----------------------------
   const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
-  if (XCD_REMAP && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  // Dense products (uniform tile cost): give each XCD a contiguous range of
+  // tiles so that its concurrent workgroups share panels in its own L2.
+  // Triangular products keep the hardware's round-robin order, which
+  // balances their uneven tile costs over the XCDs.
+  const bool remap = XCD_REMAP || !(p.flags & (G_A_LOWER | G_B_LOWER));
+  if (remap && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
   const int per_group = GROUP_M * ntn;
   const int grp = bid / per_group;
   const int first_m = grp * GROUP_M;

@@ -63,4 +63,8 @@ template <typename TL>
 hipError_t launch_sumsq_lower(const TL* L, int64_t ldl, int64_t n, double* part, double* out,
                               hipStream_t s);
 
+// Record a HIP error for trsm_last_hip_error() (thread-local); returns
+// TRSM_EHIP's numeric value for convenience.
+int note_hip_error(hipError_t e);
+
 }  // namespace trsm

@@ -101,7 +101,7 @@ class Arena {
 };
 
 struct Factor {
-  int64_t n = 0, m = 0;
+  int64_t n = 0, m = 0, n0 = 0;
   size_t off = 0, bytes = 0;
   double* L64 = nullptr;  int64_t ld64 = 0;
   float* L32 = nullptr;   int64_t ld32 = 0;
@@ -142,7 +142,6 @@ struct trsm_server_s {
   Arena arena;
   std::vector<Factor> factors;
   std::vector<hipStream_t> streams;
-  int next_stream = 0;
 
   std::mutex mu;
   std::condition_variable cv;
@@ -206,7 +205,7 @@ void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request
     ew_b.push_back(EwEntry{r.B, r.ldb, b.B64, kp, n, kp, 1.0, EW_F64_COPY, k});
     ew_in.push_back(EwEntry{r.B, r.ldb, b.Rl, kp, n, kp, 1.0, EW_F64_TO_F32, k});
     SweepItem<float> it{};
-    it.n = f.n; it.k = kp;
+    it.n = f.n; it.k = kp; it.n0 = f.n0;
     it.L = f.L32; it.ldl = f.ld32;
     it.Linv = f.Linv32;
     it.B = b.Rl; it.ldb = kp;          // the running right-hand side is updated in place
@@ -230,11 +229,11 @@ void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request
   list.clear();
   list.add_ew(ew_b);
   list.add_ew(ew_in);
-  record_sweep<float>(list, sweep, S->n0);
+  record_sweep<float>(list, sweep);
   list.add_ew(ew_x0);
   list.add_gemm64(resid);
   list.add_ew(ew_r);
-  record_sweep<float>(list, sweep, S->n0);
+  record_sweep<float>(list, sweep);
   list.add_ew(ew_add);
   list.add_ew(ew_out);
 }
@@ -270,12 +269,17 @@ void complete_batch(trsm_server_s* S, Batch& b, int status) {
   b.done = nullptr;
 }
 
-// One pass of the worker: retire finished batches, admit, launch.
+// One pass of the worker: retire finished batches, then -- if a stream is
+// free -- admit queued requests (arrival order, while slots and memory
+// allow) and launch them.  Requests that arrive while every stream is busy
+// accumulate and form a larger batch on the next free stream (continuous
+// batching: admission happens as soon as capacity frees up, and batches on
+// different streams run concurrently).
 bool worker_tick(trsm_server_s* S) {
   std::vector<std::shared_ptr<Request>> admitted;
+  std::vector<int> free_streams;
   {
     std::lock_guard<std::mutex> g(S->mu);
-    // retire
     for (size_t i = 0; i < S->inflight.size();) {
       hipError_t q = hipEventQuery(S->inflight[i].done);
       if (q == hipErrorNotReady) {
@@ -285,14 +289,18 @@ bool worker_tick(trsm_server_s* S) {
       complete_batch(S, S->inflight[i], q == hipSuccess ? TRSM_OK : TRSM_EHIP);
       S->inflight.erase(S->inflight.begin() + i);
     }
-    // admit in arrival order while slots and memory allow
+    std::vector<bool> busy(S->streams.size(), false);
+    for (const Batch& b : S->inflight) busy[b.stream] = true;
+    for (size_t i = 0; i < busy.size(); ++i)
+      if (!busy[i]) free_streams.push_back((int)i);
+    if (free_streams.empty()) return false;
     while (!S->pending.empty() && S->slots_used < S->max_slots) {
       auto rp = S->pending.front();
       const Factor& f = S->factors[rp->l_id];
       const size_t need = request_bytes(f.n, rp->kp);
       const size_t off = S->arena.alloc(need);
       if (off == SIZE_MAX) {
-        // cannot fit now; if it can never fit (nothing in flight), fail it
+        // cannot fit now; if it can never fit (nothing else holds memory), fail it
         if (S->inflight.empty() && admitted.empty()) {
           S->pending.pop_front();
           rp->state = TRSM_REQ_ERROR;
@@ -312,12 +320,20 @@ bool worker_tick(trsm_server_s* S) {
     S->max_inflight_slots = std::max(S->max_inflight_slots, S->slots_used);
   }
   if (admitted.empty()) return false;
-  // group by block count and launch each group as one batch
-  std::map<int, std::vector<std::shared_ptr<Request>>> groups;
-  for (auto& rp : admitted) groups[bucket_of(S->factors[rp->l_id].m)].push_back(rp);
-  for (auto& kv : groups) {
+  // Group by block count (small systems need few sweep phases) and merge the
+  // smallest groups until there is one group per free stream.
+  std::map<int, std::vector<std::shared_ptr<Request>>> by_bucket;
+  for (auto& rp : admitted) by_bucket[bucket_of(S->factors[rp->l_id].m)].push_back(rp);
+  std::vector<std::vector<std::shared_ptr<Request>>> groups;
+  for (auto& kv : by_bucket) groups.push_back(std::move(kv.second));
+  while (groups.size() > free_streams.size()) {
+    groups[1].insert(groups[1].end(), groups[0].begin(), groups[0].end());
+    groups.erase(groups.begin());
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
     Batch b;
-    b.reqs = kv.second;
+    b.reqs = std::move(groups[gi]);
+    b.stream = free_streams[gi];
     LaunchList list;
     record_pipeline(S, b.reqs, list);
     const size_t tb = list.table_bytes();
@@ -328,15 +344,14 @@ bool worker_tick(trsm_server_s* S) {
       b.table_off = S->arena.alloc(tb);
     }
     if (b.table_off == SIZE_MAX) status = TRSM_ENOMEM;
-    hipStream_t s = S->streams[S->next_stream];
-    b.stream = S->next_stream;
-    S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+    hipStream_t s = S->streams[b.stream];
     if (status == TRSM_OK) {
       char* dev = S->base + b.table_off;
-      if (hipMemcpyAsync(dev, b.table.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess ||
-          list.run(dev, s) != hipSuccess || hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-          hipEventRecord(b.done, s) != hipSuccess)
-        status = TRSM_EHIP;
+      hipError_t e = hipMemcpyAsync(dev, b.table.data(), tb, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = list.run(dev, s);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(b.done, s);
+      if (e != hipSuccess) status = note_hip_error(e);
     }
     std::lock_guard<std::mutex> g(S->mu);
     S->batches += 1;
@@ -406,8 +421,9 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
   if (!S || !L || !l_id || n <= 0 || ldl < n || n > (1 << 20)) return TRSM_EINVAL;
   Factor f;
   f.n = n;
-  f.m = ceil_div(n, S->n0);
-  f.bytes = factor_bytes(n, S->n0);
+  f.n0 = effective_n0(n, S->n0);
+  f.m = ceil_div(n, f.n0);
+  f.bytes = factor_bytes(n, f.n0);
   {
     std::lock_guard<std::mutex> g(S->mu);
     f.off = S->arena.alloc(f.bytes);
@@ -418,7 +434,7 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
   f.L64 = (double*)p; p += al((size_t)n * f.ld64 * 8);
   f.ld32 = round_up(n, 4);
   f.L32 = (float*)p; p += al((size_t)n * f.ld32 * 4);
-  f.Linv64 = (double*)p; p += al((size_t)f.m * S->n0 * S->n0 * 8);
+  f.Linv64 = (double*)p; p += al((size_t)f.m * f.n0 * f.n0 * 8);
   f.Linv32 = (float*)p;
   hipStream_t s = S->streams[0];
   trsm_plan_t plan = nullptr;
@@ -429,7 +445,7 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
     if (e == hipSuccess) e = launch_copy2d<double, float>(L, ldl, f.L32, f.ld32, n, n, 1.0, s);
     if (e == hipSuccess) st = trsm_invert_diag(plan, f.L64, f.ld64, f.Linv64, s);
     if (st == TRSM_OK && e == hipSuccess)
-      e = launch_convert<double, float>(f.Linv64, f.Linv32, f.m * S->n0 * S->n0, s);
+      e = launch_convert<double, float>(f.Linv64, f.Linv32, f.m * f.n0 * f.n0, s);
     if (st == TRSM_OK && e == hipSuccess) e = hipStreamSynchronize(s);
     if (st == TRSM_OK && e == hipSuccess) {
       trsm_status le;

@@ -34,6 +34,15 @@ inline trsm_status hip_fail(hipError_t e) {
   return TRSM_EHIP;
 }
 
+}  // namespace
+
+int trsm::note_hip_error(hipError_t e) {
+  g_last_hip = (int)e;
+  return (int)TRSM_EHIP;
+}
+
+namespace {
+
 #define TRSM_HIP(...)                           \
   do {                                          \
     hipError_t e_ = (__VA_ARGS__);              \

@@ -346,13 +346,15 @@ def test_batch_graph_replays_match_eager(torch, T):
     sysd, items = _batch_setup(torch, T, SHAPES[:4], "f64", n0, 90)
     b, ws, wsp = _run_batch(torch, T, items, "f64", n0)
     eager = [host(d["Xd"]).copy() for d in sysd]
-    stream = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(T.TrsmError):
+        T.trsm_batch_run(b, wsp, 0, True)     # the NULL stream cannot be captured
+    side = torch.cuda.Stream()
     for rep in range(4):
         for d in sysd:
             d["Xd"].fill_(float("nan"))       # eager work between replays
         torch.cuda.synchronize()
-        T.trsm_batch_run(b, wsp, stream, True)
-        torch.cuda.synchronize()
+        T.trsm_batch_run(b, wsp, side.cuda_stream, True)   # capture, then replays
+        side.synchronize()
         for d, X in zip(sysd, eager):
             assert np.array_equal(host(d["Xd"]), X), rep
     T.trsm_batch_destroy(b)
