@@ -81,7 +81,7 @@ template <typename P>
 std::vector<int> gemm_starts(const std::vector<P>& e, int* total) {
   std::vector<int> st(e.size() + 1, 0);
   for (size_t i = 0; i < e.size(); ++i) {
-    const int64_t tiles = ceil_div(e[i].M, kBM) * ceil_div(e[i].N, kBN);
+    const int64_t tiles = gemm_wgs(e[i].M, e[i].N, e[i].K, e[i].flags, kBM, kBN);
     st[i + 1] = st[i] + (int)tiles;
   }
   *total = st.back();
@@ -179,7 +179,7 @@ void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items) {
       p.ldb = (i == 0) ? it.ldb : it.ldr;
       p.Cout = it.X + r0 * it.ldx; p.ldco = it.ldx;
       p.M = (int)sz; p.N = (int)it.k; p.K = (int)sz;
-      p.flags = G_A_LOWER;
+      p.flags = G_A_LOWER | G_A_ZERO_UPPER;
       trmm.push_back(p);
       if (i + 1 < m) {
         // B'(T_{i+1}) = B'(T_{i+1}) - L(T_{i+1}, S_i) X(S_i)

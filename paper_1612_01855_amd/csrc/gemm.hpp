@@ -19,8 +19,11 @@
 //
 // Work decomposition: a workgroup of WGM x WGN waves owns a BM x BN tile;
 // each wave owns (BM/WGM) x (BN/WGN) made of 16x16 MFMA tiles.  K advances in
-// chunks of BK with two LDS buffers and a register prefetch of the next
-// chunk, one barrier per chunk.  Tiles are visited in groups of GROUP_M row
+// chunks of 128 bytes with two LDS stages and one barrier per chunk.  Aligned
+// binary64/binary32 products copy their operands from HBM directly into LDS
+// (buffer loads with the LDS modifier, no register staging); the general
+// path stages them through registers.  Square lower-triangular products are
+// folded so that every workgroup gets equal work.  Tiles are visited in groups of GROUP_M row
 // tiles (column-major inside a group) so that concurrently running
 // workgroups share A and B panels in L2.  The hardware deals consecutive
 // workgroup ids to the eight XCDs in turn; dense products regroup the ids so
@@ -42,6 +45,7 @@ enum GemmFlags : uint32_t {
   G_C2_T = 4u,       // C2 stored transposed: C2[col * ldc2 + row]
   G_BETA = 8u,       // read Cin
   G_ROWSCALE = 16u,  // multiply the product by rscale[row * ld_rs]
+  G_A_ZERO_UPPER = 32u,  // with G_A_LOWER: A's upper triangle is stored as zeros (no masking)
 };
 
 template <typename TIn, typename TCin, typename TCout, typename TC2>
@@ -79,13 +83,256 @@ __device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-// One BM x BN output tile of one batch entry.  `bid` is the tile's index
-// among the nwg tiles of the entry; `z` the batch index.
+
+// A square lower-triangular A (M == K) makes the tile cost grow with the
+// row index.  Such products are "folded": one workgroup computes row tile t
+// and row tile ntm-1-t of the same column, so every workgroup gets the same
+// amount of work (and half as many workgroups are launched).
+__host__ __device__ inline bool tri_fold(int M, int K, uint32_t flags, int BM) {
+  return (flags & G_A_LOWER) && M == K && (M + BM - 1) / BM >= 2;
+}
+
+// Workgroups one product needs.
+__host__ __device__ inline int gemm_wgs(int M, int N, int K, uint32_t flags, int BM, int BN) {
+  const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+  return (tri_fold(M, K, flags, BM) ? (ntm + 1) / 2 : ntm) * ntn;
+}
+
+// Row slot and column of workgroup `bid` among the nwg workgroups of one
+// product: groups of GROUP_M row slots, column-major inside a group.  The
+// hardware deals consecutive workgroup ids to the eight XCDs in turn;
+// products with uniform tile cost (dense, folded, or a single group of row
+// slots) regroup the ids so that each XCD works on a contiguous range of
+// tiles and its concurrent workgroups share panels in its own L2 (2.3x less
+// L2-miss traffic).  Other triangular products keep the round-robin order,
+// which spreads their uneven tile costs over the XCDs (a contiguous range of
+// row groups per XCD made an unfolded lower-triangular product twice as slow).
+template <int GROUP_M, bool XCD_REMAP>
+__device__ __forceinline__ void tile_slot(int rows, int ntn, bool uniform, int bid, int nwg,
+                                          int& slot, int& tn) {
+  const bool remap = XCD_REMAP || uniform || rows <= GROUP_M;
+  if (remap && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  const int per_group = GROUP_M * ntn;
+  const int grp = bid / per_group;
+  const int first_m = grp * GROUP_M;
+  const int gsize = min(rows - first_m, GROUP_M);
+  const int in_grp = bid % per_group;
+  slot = first_m + in_grp % gsize;
+  tn = in_grp / gsize;
+}
+
+// Reduction range of a tile: whole chunks of BK from kbeg, skipping the zero
+// part of a triangular operand.  Returns the number of chunks.
+template <int BM, int BK>
+__device__ __forceinline__ int chunk_range(int K, uint32_t flags, int r0, int c0, int& kbeg) {
+  int kend = K;
+  kbeg = 0;
+  if (flags & G_A_LOWER) kend = min(K, r0 + BM);
+  if (flags & G_B_LOWER) kbeg = (min(c0, K) / BK) * BK;
+  return kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+}
+
+// Epilogue: Cout = beta*Cin + alpha*rowscale*acc (+ optional second output).
+// Lane (gi, g) holds column gi and rows out_row(g, r) of every 16x16 tile.
+template <typename TIn, typename TCin, typename TCout, typename TC2, int TM, int TN, int WTM,
+          int WTN>
+__device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout, TC2>& p,
+                                              const typename Mfma<TIn>::Out (&acc)[TM][TN],
+                                              int zo, int zi, int r0, int c0, int wm, int wn,
+                                              int g, int gi) {
+  using MF = Mfma<TIn>;
+  using Acc = typename MF::Acc;
+  TCout* __restrict__ Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
+  const TCin* __restrict__ Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
+  const bool use_beta = (p.flags & G_BETA) && Ci;
+  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
+  const bool c2t = p.flags & G_C2_T;
+  // the epilogue runs in binary64 whenever C is binary64 on either side
+  using Epi = typename std::conditional<std::is_same<TCout, double>::value ||
+                                            std::is_same<TCin, double>::value,
+                                        double, Acc>::type;
+  const Epi alpha = static_cast<Epi>(p.alpha);
+  const Epi beta = static_cast<Epi>(p.beta);
+  const int M = p.M, N = p.N;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + wm * WTM + i * 16 + MF::out_row(g, r);
+      if (row >= M) continue;
+      Epi rs = Epi(1);
+      if (use_rs) rs = static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = c0 + wn * WTN + j * 16 + gi;
+        if (col >= N) continue;
+        Epi v = alpha * (static_cast<Epi>(acc[i][j][r]) * rs);
+        if (use_beta) v += beta * static_cast<Epi>(Ci[(int64_t)row * p.ldci + col]);
+        Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
+        if (p.C2) {
+          const TC2 w = cvt<TC2>(v * static_cast<Epi>(p.c2scale));
+          if (c2t) p.C2[(int64_t)col * p.ldc2 + row] = w;
+          else p.C2[(int64_t)row * p.ldc2 + col] = w;
+        }
+      }
+    }
+  }
+}
+
+// s_waitcnt immediate that waits for at most n outstanding vector-memory
+// operations and nothing else (gfx9 encoding).
+constexpr int vmcnt_imm(int n) {
+  return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8);
+}
+
+// Matrix-core tile with operands copied from HBM straight into LDS by
+// buffer loads (no register staging), two LDS stages, one barrier per chunk.
+// For one-k-per-lane instructions (binary64, binary32) with row-major B and
+// 16-byte aligned operands.  LDS layout per stage:
+//  * A: BM rows of 128 bytes (BK elements), the eight 16-byte pieces of row r
+//    stored XOR-swizzled (piece d at position d ^ (r & 7)), so that the 16
+//    rows a fragment read touches fall in different banks;
+//  * B: BK rows of BN elements; each wave load instruction writes 1 KB (one
+//    or more whole rows) and is followed by 16 bytes of padding.
+// All fragments of a half-chunk are read before its MFMAs are issued.
+// Triangular masks are applied to the fragments, only in chunks that cross
+// the diagonal.
+template <typename TIn, typename TCin, typename TCout, typename TC2, int BM, int BN, int WGM,
+          int WGN>
+__device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
+                                              const int r0, const int c0) {
+  using MF = Mfma<TIn>;
+  using Acc = typename MF::Acc;
+  using Out = typename MF::Out;
+  using V16 = typename VecOf<TIn>::T2;
+  constexpr int NW = WGM * WGN;
+  constexpr int ES = sizeof(TIn);
+  constexpr int VEC = 16 / ES;
+  constexpr int BK = 128 / ES;
+  constexpr int KL = BK / 4;                     // k per lane group per chunk (32 bytes)
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int A_BYTES = BM * 128;
+  constexpr int ROW_B = BN * ES;                 // bytes of one B row
+  constexpr int RPI = 1024 / ROW_B;              // B rows per wave instruction
+  constexpr int B_INST_TOTAL = BK / RPI;
+  constexpr int B_BYTES = B_INST_TOTAL * (1024 + 16);
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int A_INST = BM / 8 / NW;
+  constexpr int B_INST = B_INST_TOTAL / NW;
+  static_assert(MF::kPerLane == 1, "one k per lane");
+  static_assert(RPI * ROW_B == 1024, "a wave instruction must cover whole B rows");
+  static_assert(A_INST * NW * 8 == BM && B_INST * NW == B_INST_TOTAL, "even split of loads");
+  __shared__ __attribute__((aligned(1024))) char smem[2 * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN, gi = lane & 15, g = lane >> 4;
+  const int zo = z / p.zdiv, zi = z % p.zdiv;
+  const TIn* __restrict__ A = p.A + zo * p.sa_o + zi * p.sa_i;
+  const TIn* __restrict__ B = p.B + zo * p.sb_o + zi * p.sb_i;
+  const int M = p.M, N = p.N, K = p.K;
+  const int lda = (int)p.lda, ldb = (int)p.ldb;
+  int kbeg;
+  const int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
+  const bool a_lower = p.flags & G_A_LOWER;
+  const bool b_lower = p.flags & G_B_LOWER;
+
+  Out acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = Acc(0);
+
+  auto issue = [&](int c, int st) {
+    const int k0 = kbeg + c * BK;
+    char* base = smem + st * STAGE;
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (int64_t)r0 * lda + k0);
+#pragma unroll
+    for (int q = 0; q < A_INST; ++q) {
+      const int rb = 8 * (wave * A_INST + q);
+      const int r = rb + (lane >> 3);
+      const int d = (lane & 7) ^ (r & 7);
+      const bool ok = (r0 + r < M) && (k0 + d * VEC < K);
+      const int off = ok ? (r * lda + d * VEC) * ES : kBufOOB;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) void*)(base + rb * 128), 16, off, 0, 0, 0);
+    }
+    const __amdgpu_buffer_rsrc_t rbs = make_rsrc(B + (int64_t)k0 * ldb + c0);
+#pragma unroll
+    for (int q = 0; q < B_INST; ++q) {
+      const int qi = wave * B_INST + q;
+      const int kr = qi * RPI + lane / (64 / RPI);
+      const int cv = (lane % (64 / RPI)) * VEC;
+      const bool ok = (k0 + kr < K) && (c0 + cv < N);
+      const int off = ok ? (kr * ldb + cv) * ES : kBufOOB;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rbs, (__attribute__((address_space(3))) void*)(base + A_BYTES + qi * (1024 + 16)), 16,
+          off, 0, 0, 0);
+    }
+  };
+
+  if (nchunks > 0) issue(0, 0);
+  for (int c = 0; c < nchunks; ++c) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));   // this wave's part of chunk c has landed
+    __syncthreads();                            // ... everyone's; and chunk c-1 is consumed
+    if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+    const char* as = smem + (c & 1) * STAGE;
+    const char* bs = as + A_BYTES;
+    const int k0 = kbeg + c * BK;
+    const bool mask_a = a_lower && !(p.flags & G_A_ZERO_UPPER) && (k0 + BK - 1 > r0 + wm * WTM);
+    const bool mask_b = b_lower && (k0 < c0 + wn * WTN + WTN - 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {               // the lane group's two 16-byte pieces of k
+      V16 fa[TM];
+      TIn fb[VEC][TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm * WTM + i * 16 + gi;
+        const int slot = (2 * g + h) ^ (r & 7);
+        fa[i] = *reinterpret_cast<const V16*>(as + r * 128 + slot * 16);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int kr = g * KL + h * VEC + e;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          fb[e][j] = *reinterpret_cast<const TIn*>(bs + (kr / RPI) * (1024 + 16) +
+                                                   (kr % RPI) * ROW_B +
+                                                   (wn * WTN + j * 16 + gi) * ES);
+      }
+      if (mask_a) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (k0 + g * KL + h * VEC + e > r0 + wm * WTM + i * 16 + gi) fa[i][e] = TIn(0);
+      }
+      if (mask_b) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (k0 + g * KL + h * VEC + e < c0 + wn * WTN + j * 16 + gi) fb[e][j] = TIn(0);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[i][e], fb[e][j], acc[i][j]);
+    }
+  }
+  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, r0, c0, wm, wn, g, gi);
+}
+
+// Register-staged tile: every operand layout and alignment (the general
+// path; bfloat16/half products with k-contiguous B, and unaligned operands).
 template <typename TIn, typename TCin, typename TCout, typename TC2,
-          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
-          int GROUP_M = 8, bool XCD_REMAP = false>
-__device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
-                                          int bid, int nwg) {
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+__device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCout, TC2>& p,
+                                                 int z, const int r0, const int c0) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
   using Out = typename MF::Out;
@@ -125,29 +372,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
   const int M = p.M, N = p.N, K = p.K;
   const int64_t lda = p.lda, ldb = p.ldb;
 
-  // ---- tile coordinates (XCD-aware, grouped) -----------------------------
-  const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
-  // Dense products (uniform tile cost): give each XCD a contiguous range of
-  // tiles so that its concurrent workgroups share panels in its own L2.
-  // Triangular products keep the hardware's round-robin order, which
-  // balances their uneven tile costs over the XCDs.
-  const bool remap = XCD_REMAP || !(p.flags & (G_A_LOWER | G_B_LOWER));
-  if (remap && (nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
-  const int per_group = GROUP_M * ntn;
-  const int grp = bid / per_group;
-  const int first_m = grp * GROUP_M;
-  const int gsize = min(ntm - first_m, GROUP_M);
-  const int in_grp = bid % per_group;
-  const int tm = first_m + in_grp % gsize;
-  const int tn = in_grp / gsize;
-  const int r0 = tm * BM, c0 = tn * BN;
-
   const bool a_lower = p.flags & G_A_LOWER;
   const bool b_lower = p.flags & G_B_LOWER;
-  int kbeg = 0, kend = K;
-  if (a_lower) kend = min(K, r0 + BM);
-  if (b_lower) kbeg = (min(c0, K) / BK) * BK;
-  const int nchunks = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  int kbeg;
+  const int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
 
   Out acc[TM][TN];
 #pragma unroll
@@ -296,40 +524,34 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
     }
   }
 
-  // ---- epilogue ---------------------------------------------------------
-  TCout* __restrict__ Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
-  const TCin* __restrict__ Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
-  const bool use_beta = (p.flags & G_BETA) && Ci;
-  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
-  const bool c2t = p.flags & G_C2_T;
-  // the epilogue runs in binary64 whenever C is binary64 on either side
-  using Epi = typename std::conditional<std::is_same<TCout, double>::value ||
-                                            std::is_same<TCin, double>::value,
-                                        double, Acc>::type;
-  const Epi alpha = static_cast<Epi>(p.alpha);
-  const Epi beta = static_cast<Epi>(p.beta);
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = r0 + wm * WTM + i * 16 + MF::out_row(g, r);
-      if (row >= M) continue;
-      Epi rs = Epi(1);
-      if (use_rs) rs = static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int col = c0 + wn * WTN + j * 16 + gi;
-        if (col >= N) continue;
-        Epi v = alpha * (static_cast<Epi>(acc[i][j][r]) * rs);
-        if (use_beta) v += beta * static_cast<Epi>(Ci[(int64_t)row * p.ldci + col]);
-        Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
-        if (p.C2) {
-          const TC2 w = cvt<TC2>(v * static_cast<Epi>(p.c2scale));
-          if (c2t) p.C2[(int64_t)col * p.ldc2 + row] = w;
-          else p.C2[(int64_t)row * p.ldc2 + col] = w;
-        }
-      }
-    }
+  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, r0, c0, wm, wn, g, gi);
+}
+
+
+// The output tiles of workgroup `bid` (of nwg) of one batch entry z: one
+// tile, or two for a folded triangular product.
+template <typename TIn, typename TCin, typename TCout, typename TC2,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
+          int GROUP_M = 8, bool XCD_REMAP = false>
+__device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
+                                          int bid, int nwg) {
+  const int ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
+  const bool fold = tri_fold(p.M, p.K, p.flags, BM);
+  const bool uniform = fold || !(p.flags & (G_A_LOWER | G_B_LOWER));
+  const int rows = fold ? (ntm + 1) / 2 : ntm;
+  int slot, tn;
+  tile_slot<GROUP_M, XCD_REMAP>(rows, ntn, uniform, bid, nwg, slot, tn);
+  auto one = [&](int tm) {
+    if constexpr (ALIGNED && !BKMAJOR && Mfma<TIn>::kPerLane == 1)
+      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, tm * BM, tn * BN);
+    else
+      gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, tm * BM,
+                                                                               tn * BN);
+  };
+  one(slot);
+  if (fold && ntm - 1 - slot != slot) {
+    __syncthreads();   // the second tile reuses the LDS stages
+    one(ntm - 1 - slot);
   }
 }
 
@@ -357,7 +579,7 @@ void gemm_grouped_kernel(const GemmParams<TIn, TCin, TCout, TC2>* __restrict__ e
     else hi = mid - 1;
   }
   const GemmParams<TIn, TCin, TCout, TC2>& p = entries[lo];
-  const int tiles = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
+  const int tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
   const int local = b - tile_start[lo];
   gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, local / tiles,
                                                                       local % tiles, tiles);
@@ -384,7 +606,7 @@ inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int ba
                               hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
   const bool aligned = gemm_aligned<TIn, BM, BN, BKMAJOR>(p);
-  const int64_t tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
+  const int64_t tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
   dim3 grid((unsigned)tiles, 1, (unsigned)batch);
   dim3 block(WGM * WGN * 64);
   if (aligned)

@@ -156,6 +156,9 @@ struct trsm_plan_s {
   size_t ws_bytes = 0;
   unsigned long long* d_bad = nullptr;   // first singular row (device word)
   LaunchTimer timer;
+  // lookahead: a second stream and the events that order the two
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> events;
 };
 
 // ---------------------------------------------------------------------------
@@ -289,7 +292,7 @@ hipError_t rec_tri_inv_levels(double* Linv, int64_t n0, int64_t m, int64_t nb, h
 namespace {
 
 template <typename T>
-trsm_status sweep_right(const trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, const T* B,
+trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, const T* B,
                         int64_t ldb, T* X, int64_t ldx, T* R, hipStream_t s) {
   const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
   const bool alias = (const void*)X == (const void*)B;
@@ -300,19 +303,69 @@ trsm_status sweep_right(const trsm_plan_s& P, const T* L, int64_t ldl, const T* 
     src0 = R;
     ld_src0 = k;
   }
+  // Lookahead over two streams.  Stream s carries the critical chain
+  //   diag apply i -> update of the next block rows S_{i+1} -> diag apply i+1,
+  // stream `side` carries the update of the remaining rows T_{i+2}, which
+  // therefore overlaps the next diagonal apply.  Events order the two:
+  //   side waits for the diag apply i (it reads X(S_i));
+  //   s waits for side's update i-1 before updating rows S_{i+1} (both
+  //   update those rows, read-modify-write).
+  const bool look = m > 2;
+  if (look) {
+    if (!P.side) TRSM_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+    const size_t need = (size_t)(2 * m + 2);
+    while (P.events.size() < need) {
+      hipEvent_t e;
+      TRSM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      P.events.push_back(e);
+    }
+  }
+  hipEvent_t* ev_x = look ? P.events.data() : nullptr;        // diag apply i done (on s)
+  hipEvent_t* ev_b = look ? P.events.data() + m : nullptr;    // side update i done
+  hipEvent_t ev_start = look ? P.events[2 * m] : nullptr;
+  hipEvent_t ev_end = look ? P.events[2 * m + 1] : nullptr;
+  hipStream_t s2 = P.side;
+  if (look) {
+    TRSM_HIP(hipEventRecord(ev_start, s));
+    TRSM_HIP(hipStreamWaitEvent(s2, ev_start, 0));
+  }
   for (int64_t i = 0; i < m; ++i) {
     const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
     const T* src = (i == 0) ? src0 + r0 * ld_src0 : R + r0 * k;
     const int64_t ld_src = (i == 0) ? ld_src0 : k;
+    // X(S_i) = Linv_ii * B'(S_i)
     TRSM_HIP(gemm_simple<T>(Linv + i * n0 * n0, n0, src, ld_src, nullptr, 0, X + r0 * ldx, ldx,
-                            sz, k, sz, 1.0, 0.0, G_A_LOWER, s));
-    if (i + 1 < m) {
-      const int64_t t0 = r0 + n0, rows = n - t0;
-      const T* cin = (i == 0) ? B + t0 * ldb : R + t0 * k;
-      const int64_t ldci = (i == 0) ? ldb : k;
+                            sz, k, sz, 1.0, 0.0, G_A_LOWER | G_A_ZERO_UPPER, s));
+    if (i + 1 >= m) break;
+    const int64_t t0 = r0 + n0;
+    const T* cin = (i == 0) ? B + t0 * ldb : R + t0 * k;
+    const int64_t ldci = (i == 0) ? ldb : k;
+    if (!look) {
+      // B'(T_{i+1}) -= L(T_{i+1}, S_i) X(S_i)
       TRSM_HIP(gemm_simple<T>(L + t0 * ldl + r0, ldl, X + r0 * ldx, ldx, cin, ldci, R + t0 * k, k,
-                              rows, k, sz, -1.0, 1.0, 0u, s));
+                              n - t0, k, sz, -1.0, 1.0, 0u, s));
+      continue;
     }
+    TRSM_HIP(hipEventRecord(ev_x[i], s));
+    // rows S_{i+1} on the critical stream
+    if (i >= 1) TRSM_HIP(hipStreamWaitEvent(s, ev_b[i - 1], 0));
+    const int64_t rows_a = std::min(n0, n - t0);
+    TRSM_HIP(gemm_simple<T>(L + t0 * ldl + r0, ldl, X + r0 * ldx, ldx, cin, ldci, R + t0 * k, k,
+                            rows_a, k, sz, -1.0, 1.0, 0u, s));
+    // rows T_{i+2} on the side stream
+    const int64_t t1 = t0 + rows_a;
+    if (t1 < n) {
+      TRSM_HIP(hipStreamWaitEvent(s2, ev_x[i], 0));
+      TRSM_HIP(gemm_simple<T>(L + t1 * ldl + r0, ldl, X + r0 * ldx, ldx, cin + rows_a * ldci, ldci,
+                              R + t1 * k, k, n - t1, k, sz, -1.0, 1.0, 0u, s2));
+      TRSM_HIP(hipEventRecord(ev_b[i], s2));
+    } else {
+      TRSM_HIP(hipEventRecord(ev_b[i], s2));
+    }
+  }
+  if (look) {
+    TRSM_HIP(hipEventRecord(ev_end, s2));
+    TRSM_HIP(hipStreamWaitEvent(s, ev_end, 0));
   }
   return TRSM_OK;
 }
@@ -357,7 +410,7 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.Cout = D + r0 * k; p.ldco = k;
       p.C2 = XlowT + r0; p.ldc2 = n;
       p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
-      p.flags = G_A_LOWER | G_C2_T;
+      p.flags = G_A_LOWER | G_A_ZERO_UPPER | G_C2_T;
       TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
         return launch_gemm<float, float, float, TL, 128, 128, 2, 2, false>(p, 1, s);
       }));
@@ -586,6 +639,8 @@ trsm_status trsm_plan_destroy(trsm_plan_t P) {
   if (!P) return TRSM_OK;
   if (P->d_bad) (void)hipFree(P->d_bad);
   P->timer.release();
+  for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
+  if (P->side) (void)hipStreamDestroy(P->side);
   delete P;
   return TRSM_OK;
 }
