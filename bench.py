@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--k", type=int, default=16384)
     ap.add_argument("--n0", type=int, default=0)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--lookahead", action="store_true",
+                    help="two-stream lookahead sweep (per-launch timings then overlap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -248,7 +250,8 @@ def main():
     Xd = torch.empty_like(Bd)
     torch.cuda.synchronize()
 
-    solver = T.Solver.create(n, k, args.precision, args.n0, 0, device=dev)
+    solver = T.Solver.create(n, k, args.precision, args.n0,
+                             T.FLAG_LOOKAHEAD if args.lookahead else 0, device=dev)
     info = solver.info
     stream = torch.cuda.current_stream(dev)
     log(f"plan: n0={info.n0} m={info.m} (paper rule n0={info.n0_paper_rule}); "
@@ -367,7 +370,8 @@ def main():
         "config": {"workload": workload, "n": n, "k": k, "n0": info.n0, "m": info.m,
                    "n0_paper_rule": info.n0_paper_rule, "precision": args.precision,
                    "L": "diag U[1,2], strict lower U[-1,1]/n", "B": "N(0,1)", "seed": args.seed,
-                   "step": "trsm_invert_diag + trsm_solve (right-looking sweep)",
+                   "step": "trsm_invert_diag + trsm_solve (right-looking sweep"
+                           + (", two-stream lookahead)" if args.lookahead else ")"),
                    "inversion_flops_per_step": info.inv_flops},
         "roofline": roofline,
         "cpu_baseline": cpu,

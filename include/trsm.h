@@ -60,6 +60,9 @@ typedef enum trsm_precision {
 /* Plan flags. */
 #define TRSM_FLAG_NO_REFINE   0x1u  /* mixed modes: return the unrefined low-precision solve */
 #define TRSM_FLAG_RECURSIVE   0x2u  /* solve with the recursive baseline (Alg. Rec-TRSM order) */
+#define TRSM_FLAG_LOOKAHEAD   0x4u  /* F64/F32 sweep: update the next block's rows first and the
+                                       rest on a second stream, overlapping the next diagonal
+                                       apply (launch timings then overlap) */
 
 typedef struct trsm_plan_s* trsm_plan_t;
 

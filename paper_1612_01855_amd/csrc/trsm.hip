@@ -310,7 +310,7 @@ trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, 
   //   side waits for the diag apply i (it reads X(S_i));
   //   s waits for side's update i-1 before updating rows S_{i+1} (both
   //   update those rows, read-modify-write).
-  const bool look = m > 2;
+  const bool look = (P.flags & TRSM_FLAG_LOOKAHEAD) && m > 2;
   if (look) {
     if (!P.side) TRSM_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     const size_t need = (size_t)(2 * m + 2);
@@ -557,7 +557,7 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   if (prec != TRSM_F64 && prec != TRSM_F32 && !is_mixed(prec)) return TRSM_EINVAL;
   if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
-  if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE)) return TRSM_EINVAL;
+  if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD)) return TRSM_EINVAL;
   if (n * k > ((int64_t)1 << 31) - 1 || n * n > ((int64_t)1 << 31) * 8) return TRSM_EINVAL;
   trsm_plan_s* P = new (std::nothrow) trsm_plan_s();
   if (!P) return TRSM_ENOMEM;

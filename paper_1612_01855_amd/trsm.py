@@ -28,6 +28,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16}
 # plan flags
 FLAG_NO_REFINE = 0x1
 FLAG_RECURSIVE = 0x2
+FLAG_LOOKAHEAD = 0x4
 
 
 class PlanInfo(ctypes.Structure):

@@ -43,7 +43,7 @@ def test_status_strings(T):
 
 
 @pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
-                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80),
+                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x8),
                                   (8, 8, 2, 0, 2)])
 def test_plan_rejects_bad_arguments(T, args):
     with pytest.raises(T.TrsmError) as e:

@@ -360,3 +360,15 @@ def test_batch_graph_replays_match_eager(torch, T):
     T.trsm_batch_destroy(b)
     for d in sysd:
         d["s"].close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lookahead_sweep_matches(torch, T, prec):
+    n, k = 1500, 70
+    L, B = gen.easy_system(n, k, 81, upper=np.nan)
+    X0 = gpu_solve(torch, T, L, B, precision=prec, n0=128)
+    X1 = gpu_solve(torch, T, L, B, precision=prec, n0=128, flags=T.FLAG_LOOKAHEAD)
+    # same products, only split differently over two streams
+    assert np.array_equal(X0, X1)
+    if prec == "f64":
+        assert oracle.rel_fro_err(X1, oracle.trsm(L, B)) <= TOL64
