@@ -192,6 +192,126 @@ def serving_bench(args, torch, T, gen, dev):
         T.trsm_server_destroy(srv)
 
 
+def time_solves(T, torch, dev, L64, B64, precision, n0, flags, reps, invert_each=True):
+    """Median milliseconds of (invert + solve) over `reps` runs, plus the plan."""
+    import numpy as np
+    n, k = B64.shape
+    dt = torch.float32 if precision == "f32" else torch.float64
+    Ld = L64.to(dt)
+    Bd = B64.to(dt)
+    Xd = torch.empty_like(Bd)
+    s = T.Solver.create(n, k, precision, n0, flags, device=dev)
+    rec = bool(flags & T.FLAG_RECURSIVE)
+    if not rec:
+        s.invert(Ld)
+    s.solve(Ld, Bd, Xd)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if not rec and invert_each:
+            s.invert(Ld)
+        s.solve(Ld, Bd, Xd)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    info = s.info
+    s.close()
+    del Ld, Bd
+    return float(np.median(times)), info, Xd
+
+
+def run_suite(args, torch, T, gen, dev):
+    """The workload sweeps: n0 sweep and the recursive baseline at n = k = 8192
+    (binary64 and binary32), the n/k sweep at n = 16384, and the hard factor in
+    mixed precision.  One JSON line per measurement."""
+    out = []
+
+    def emit(rec):
+        print(json.dumps(rec), flush=True)
+        out.append(rec)
+
+    # n0 sweep at n = k = 8192 (easy L), plus the recursive baseline
+    n = k = 8192
+    L, B = gen.easy_system(n, k, args.seed)
+    L64 = torch.from_numpy(L).to(dev)
+    B64 = torch.from_numpy(B).to(dev)
+    del L, B
+    for prec in ("f64", "f32"):
+        peak = PEAK[prec]
+        for n0 in (64, 128, 256, 512, 1024, 8192, 0):
+            ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, n0, 0, 3)
+            tf = float(n) * n * k / (ms * 1e-3) / 1e12
+            emit({"suite": "n0_sweep", "n": n, "k": k, "precision": prec,
+                  "n0": int(info.n0), "auto": n0 == 0, "ms": round(ms, 3),
+                  "tflops_n2k": round(tf, 2), "frac_peak": round(tf / peak, 4),
+                  "inversion_flops_share": round(info.inv_flops / info.solve_flops, 5)})
+            log(f"suite n0 {prec} n0={info.n0}: {ms:.2f} ms {tf:.2f} TF")
+        ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, 0, T.FLAG_RECURSIVE, 2)
+        tf = float(n) * n * k / (ms * 1e-3) / 1e12
+        emit({"suite": "recursive_baseline", "n": n, "k": k, "precision": prec,
+              "leaf": 64, "ms": round(ms, 3), "tflops_n2k": round(tf, 2),
+              "frac_peak": round(tf / peak, 4)})
+        log(f"suite recursive {prec}: {ms:.2f} ms {tf:.2f} TF")
+    del L64, B64
+    torch.cuda.empty_cache()
+
+    # n/k sweep at n = 16384, L the Cholesky factor of G G^T / 2n + I
+    n = 16384
+    L64 = gen.chol_lower_on(torch, dev, n, args.seed)
+    for k in (128, 2048, 32768):
+        B64 = torch.from_numpy(gen.rhs(n, k, args.seed)).to(dev)
+        for prec in ("f64", "f32"):
+            es = 4 if prec == "f32" else 8
+            ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, 0, 0, 3)
+            tf = float(n) * n * k / (ms * 1e-3) / 1e12
+            alg_bytes = es * (n * (n + 1) / 2 + 2 * n * k)
+            emit({"suite": "nk_sweep", "n": n, "k": k, "precision": prec, "n0": int(info.n0),
+                  "n0_paper_rule": int(info.n0_paper_rule), "ms": round(ms, 3),
+                  "tflops_n2k": round(tf, 2), "frac_peak": round(tf / PEAK[prec], 4),
+                  "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1)})
+            log(f"suite nk {prec} k={k} n0={info.n0}: {ms:.2f} ms {tf:.2f} TF "
+                f"{alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+        del B64
+        torch.cuda.empty_cache()
+    del L64
+    torch.cuda.empty_cache()
+
+    # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)
+    n = k = 16384
+    L64 = gen.chol_lower_on(torch, dev, n, args.seed, ratio=1e-12)
+    B64 = torch.from_numpy(gen.rhs(n, k, args.seed)).to(dev)
+    ms64, _, X64 = time_solves(T, torch, dev, L64, B64, "f64", 0, 0, 3)
+    nx = torch.linalg.norm(X64).item()
+    for prec in ("bf16", "f16"):
+        s = T.Solver.create(n, k, prec, 0, 0, device=dev)
+        X = torch.empty_like(B64)
+        inf = T.Info()
+        stream = torch.cuda.current_stream().cuda_stream
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.invert(L64)
+            st = T.trsm_solve(s.plan, L64.data_ptr(), n, s.linv_ptr, B64.data_ptr(), k,
+                              X.data_ptr(), k, s.workspace_ptr, stream, inf)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        diff = float(torch.linalg.norm(X - X64).item() / nx)
+        ms = sorted(times)[1]
+        emit({"suite": "mixed_hard", "n": n, "k": k, "precision": prec,
+              "status": T.status_string(st), "corrections": inf.iterations,
+              "unrefined_error": inf.unrefined_error, "backward_error": inf.backward_error,
+              "rel_diff_vs_f64_solve": diff, "ms": round(ms, 3), "f64_ms": round(ms64, 3)})
+        log(f"suite mixed hard {prec}: {T.status_string(st)}, {inf.iterations} corrections, "
+            f"{ms:.1f} ms (f64 {ms64:.1f} ms), diff vs f64 {diff:.2e}")
+        s.close()
+        del X
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +334,17 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device 3 times (reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the headline step, run the workload sweeps (one JSON line each)")
     args = ap.parse_args()
+
+    if args.suite:
+        import torch
+        from paper_1612_01855_amd import inputs as gen
+        from paper_1612_01855_amd import trsm as T
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        run_suite(args, torch, T, gen, torch.device("cuda:0"))
+        return
 
     if args.calibrate_copy:
         import torch

@@ -38,8 +38,8 @@ def rng(seed: int) -> np.random.Generator:
 def _fill_upper(L: np.ndarray, upper: Optional[float]) -> np.ndarray:
     """Write ``upper`` strictly above the diagonal (NaN proves it is unread)."""
     if upper is not None:
-        iu = np.triu_indices(L.shape[0], 1)
-        L[iu] = upper
+        for i in range(L.shape[0] - 1):
+            L[i, i + 1:] = upper
     return L
 
 
@@ -96,6 +96,38 @@ def hard_lower(n: int, seed: int, upper: Optional[float] = 0.0,
     A[np.arange(n), np.arange(n)] += ratio * lam
     L = np.linalg.cholesky(A)
     return _fill_upper(np.ascontiguousarray(L), upper)
+
+
+def chol_lower_on(torch, device, n: int, seed: int, m: Optional[int] = None,
+                  ratio: Optional[float] = None):
+    """The Cholesky-family factors at sizes where forming G G^T on the host is
+    slow: the same seeded G as chol_lower / hard_lower (host generator), the
+    product and the factorisation done by torch on `device`.  ratio=None gives
+    chol_lower's A = G G^T / m + I (m = 2n by default); a ratio gives
+    hard_lower's A = G G^T / m + ratio * lambda_max I (m = n/2 by default,
+    lambda_max by 50 seeded power iterations).  Returns a float64 tensor on
+    `device`, zeros above the diagonal.  The rounding of the product differs
+    from the host versions, so the factor is not bit-identical to them."""
+    if m is None:
+        m = 2 * n if ratio is None else max(n // 2, 1)
+    g = rng(seed)
+    G = torch.from_numpy(g.standard_normal(size=(n, m))).to(device)
+    A = G @ G.t().contiguous()
+    del G
+    A *= 1.0 / m
+    if ratio is None:
+        A.diagonal().add_(1.0)
+    else:
+        v = torch.from_numpy(g.standard_normal(size=n)).to(device)
+        lam = 0.0
+        for _ in range(50):
+            w = A @ v
+            lam = float(torch.linalg.norm(w).item())
+            v = w / lam
+        A.diagonal().add_(ratio * lam)
+    L = torch.linalg.cholesky(A)
+    del A
+    return L.tril_().contiguous()
 
 
 # ---- closed-form matrices (pins) -------------------------------------------
