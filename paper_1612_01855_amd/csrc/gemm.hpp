@@ -56,6 +56,7 @@ struct GemmParams {
   TCout* Cout; int64_t ldco; int64_t sco_o, sco_i;
   TC2* C2; int64_t ldc2;
   const float* rscale; int64_t ld_rs;
+  const float* ascale;        // if set, alpha is multiplied by *ascale (device value)
   int M, N, K;
   int zdiv;
   double alpha, beta;
@@ -151,7 +152,8 @@ __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout,
   using Epi = typename std::conditional<std::is_same<TCout, double>::value ||
                                             std::is_same<TCin, double>::value,
                                         double, Acc>::type;
-  const Epi alpha = static_cast<Epi>(p.alpha);
+  Epi alpha = static_cast<Epi>(p.alpha);
+  if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
   const Epi beta = static_cast<Epi>(p.beta);
   const int M = p.M, N = p.N;
 #pragma unroll

@@ -142,6 +142,64 @@ __global__ __launch_bounds__(256) void lowcopy_kernel(const double* __restrict__
   if (lane == 0) rscale[r * m + c] = ldexpf(1.0f, -e);
 }
 
+// Largest |D| over a rows x cols block as float bits: the bit patterns of
+// non-negative floats order like their values (and a NaN orders above
+// infinity, so it is not lost).  out[0] must start at zero.
+__global__ __launch_bounds__(256) void absmax_bits_kernel(const float* __restrict__ D, int64_t ldd,
+                                                          int64_t rows, int64_t cols,
+                                                          unsigned* __restrict__ out) {
+  __shared__ unsigned wmax[4];
+  unsigned mx = 0;
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e - r * cols;
+    mx = max(mx, __float_as_uint(D[r * ldd + c]) & 0x7FFFFFFFu);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (unsigned)__shfl_xor((int)mx, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (mx) atomicMax(out, mx);
+  }
+}
+
+__global__ void fill_u32_kernel(unsigned* __restrict__ p, int64_t count, unsigned v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// XT[c * ldx + r] = low(2^e * D[r * ldd + c]) with 2^e putting the block's
+// largest magnitude in [2^etarget, 2^(etarget+1)); *xinv = 2^-e.  64 x 64
+// tiles transposed through LDS.
+template <typename TO>
+__global__ __launch_bounds__(256) void lowx_kernel(const float* __restrict__ D, int64_t ldd,
+                                                   int64_t rows, int64_t cols, TO* __restrict__ XT,
+                                                   int64_t ldx, const unsigned* __restrict__ amax,
+                                                   float* __restrict__ xinv, int etarget) {
+  __shared__ float tile[64][65];
+  const float mx = __uint_as_float(*amax);
+  int e = 0;
+  if (mx > 0.0f && isfinite(mx)) e = etarget - ilogbf(mx);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *xinv = ldexpf(1.0f, -e);
+  const int64_t ntc = (cols + 63) / 64;
+  const int64_t tr = (blockIdx.x / ntc) * 64, tc = (blockIdx.x % ntc) * 64;
+  const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int64_t r = tr + hi + 4 * j, c = tc + lo;
+    tile[hi + 4 * j][lo] = (r < rows && c < cols) ? D[r * ldd + c] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int64_t c = tc + hi + 4 * j, r = tr + lo;
+    if (r < rows && c < cols) XT[c * ldx + r] = cvt<TO>(ldexpf(tile[lo][hi + 4 * j], e));
+  }
+}
+
 // Recursive baseline leaf: forward substitution, one thread per column.
 template <typename T>
 __global__ __launch_bounds__(64) void subst_leaf_kernel(const T* __restrict__ L, int64_t ldl,
@@ -310,6 +368,26 @@ template hipError_t launch_lowcopy<bf16_t>(const double*, int64_t, int64_t, int6
                                            bf16_t*, float*, float, hipStream_t);
 template hipError_t launch_lowcopy<f16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
                                           f16_t*, float*, float, hipStream_t);
+
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_u32_kernel<<<(unsigned)ceil_div(count, 256), 256, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_lowx(const float* D, int64_t ldd, int64_t rows, int64_t cols, TO* XT,
+                       int64_t ldx, unsigned* amax, float* xinv, int etarget, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  absmax_bits_kernel<<<grid_for(rows * cols, 256, 2048), 256, 0, s>>>(D, ldd, rows, cols, amax);
+  const int64_t tiles = ceil_div(rows, 64) * ceil_div(cols, 64);
+  lowx_kernel<TO><<<(unsigned)tiles, 256, 0, s>>>(D, ldd, rows, cols, XT, ldx, amax, xinv, etarget);
+  return hipGetLastError();
+}
+template hipError_t launch_lowx<bf16_t>(const float*, int64_t, int64_t, int64_t, bf16_t*, int64_t,
+                                        unsigned*, float*, int, hipStream_t);
+template hipError_t launch_lowx<f16_t>(const float*, int64_t, int64_t, int64_t, f16_t*, int64_t,
+                                       unsigned*, float*, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_subst_leaf(const T* L, int64_t ldl, T* X, int64_t ldx, int64_t nb, int64_t k,

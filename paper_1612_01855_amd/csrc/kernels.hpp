@@ -43,6 +43,16 @@ template <typename TO>
 hipError_t launch_lowcopy(const double* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
                           TO* Llow, float* rscale, float target, hipStream_t s);
 
+// Low-precision, transposed copy of a solved block of X with a power-of-two
+// scale taken from the block's largest magnitude (found on the device):
+// XT[c*ldx + r] = low(2^e * D[r*ldd + c]), 2^e placing the largest magnitude
+// in [2^etarget, 2^(etarget+1)); writes *xinv = 2^-e (exact inverse).
+// *amax is working space and must be zero on entry (launch_fill_u32).
+template <typename TO>
+hipError_t launch_lowx(const float* D, int64_t ldd, int64_t rows, int64_t cols, TO* XT,
+                       int64_t ldx, unsigned* amax, float* xinv, int etarget, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s);
+
 // Forward substitution on an nb x nb lower-triangular leaf (nb <= 64) for k
 // right-hand-side columns, in place on X: the recursive baseline's base case
 // (no inversion).  One thread per column.

@@ -152,7 +152,8 @@ struct trsm_plan_s {
   size_t off_linv64 = 0, off_linv32 = 0, off_llow = 0, off_rscale = 0, off_lnorm = 0, off_lpart = 0;
   size_t linv_bytes = 0;
   // workspace layout (byte offsets)
-  size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_part = 0, ws_norm = 0;
+  size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_xsc = 0, ws_part = 0,
+         ws_norm = 0;
   size_t ws_bytes = 0;
   unsigned long long* d_bad = nullptr;   // first singular row (device word)
   LaunchTimer timer;
@@ -397,25 +398,31 @@ trsm_status rec_solve(int64_t n, int64_t k, const T* L, int64_t ldl, T* X, int64
 template <typename TL>
 trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
                       const float* rscale, const double* rhs, int64_t ldr, double scale, float* Rl,
-                      float* D, TL* XlowT, hipStream_t s) {
+                      float* D, TL* XlowT, unsigned* amax, float* xinv, hipStream_t s) {
   const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
+  // largest magnitude of a solved block -> [2^etarget, 2^(etarget+1)) in the
+  // low copy: half keeps headroom below its largest finite value (65504)
+  const int etarget = std::is_same<TL, f16_t>::value ? 14 : 0;
   TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
+  TRSM_HIP(launch_fill_u32(amax, m, 0u, s));
   for (int64_t i = 0; i < m; ++i) {
     const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
-    // D(S_i) = Linv32_ii * Rl(S_i); also XlowT(:, S_i) = low(D(S_i))^T
+    // D(S_i) = Linv32_ii * Rl(S_i)
     {
-      auto p = gemm_params<float, float, float, TL>();
+      auto p = gemm_params<float, float, float, float>();
       p.A = Linv32 + i * n0 * n0; p.lda = n0;
       p.B = Rl + r0 * k; p.ldb = k;
       p.Cout = D + r0 * k; p.ldco = k;
-      p.C2 = XlowT + r0; p.ldc2 = n;
       p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
-      p.flags = G_A_LOWER | G_A_ZERO_UPPER | G_C2_T;
+      p.flags = G_A_LOWER | G_A_ZERO_UPPER;
       TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
-        return launch_gemm<float, float, float, TL, 128, 128, 2, 2, false>(p, 1, s);
+        return launch_gemm<float, float, float, float, 128, 128, 2, 2, false>(p, 1, s);
       }));
     }
     if (i + 1 < m) {
+      // XlowT(:, S_i) = low(2^e D(S_i))^T, then Rl(T_i+1) -= Llow * X(S_i)
+      TRSM_HIP(launch_lowx<TL>(D + r0 * k, k, sz, k, XlowT + r0, n, amax + i, xinv + i, etarget,
+                               s));
       const int64_t t0 = r0 + n0, rows = n - t0;
       auto p = gemm_params<TL, float, float, float>();
       p.A = Llow + t0 * n + r0; p.lda = n;
@@ -423,6 +430,7 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.Cin = Rl + t0 * k; p.ldci = k;
       p.Cout = Rl + t0 * k; p.ldco = k;
       p.rscale = rscale + t0 * m + i; p.ld_rs = m;
+      p.ascale = xinv + i;                    // undo the block's scale
       p.M = (int)rows; p.N = (int)k; p.K = (int)sz;
       p.alpha = -1.0; p.beta = 1.0;
       p.flags = G_BETA | G_ROWSCALE;
@@ -452,6 +460,8 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   float* Rl = (float*)(ws + P.ws_rl);
   float* D = (float*)(ws + P.ws_d);
   TL* XlowT = (TL*)(ws + P.ws_xlow);
+  unsigned* amax = (unsigned*)(ws + P.ws_xsc);
+  float* xinv = (float*)(ws + P.ws_xsc + 4 * P.m);
   double* part = (double*)(ws + P.ws_part);
   double* dnorm = (double*)(ws + P.ws_norm);
 
@@ -467,7 +477,7 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   const double u = ldexp(1.0, -53);
 
   double scale = pow2_scale_for(h[1]);
-  TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, s));
+  TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, amax, xinv, s));
   TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, true, s));
   if (info) {
     info->iterations = 0;
@@ -498,7 +508,7 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
       return TRSM_OK;
     }
     scale = pow2_scale_for(h[1]);
-    TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, R64, k, scale, Rl, D, XlowT, s));
+    TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, R64, k, scale, Rl, D, XlowT, amax, xinv, s));
     TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, false, s));
     // ||D|| (binary32 values, exact in binary64) for the stopping test
     TRSM_HIP(launch_copy2d<float, double>(D, k, R64, k, n, k, 1.0 / scale, s));
@@ -608,6 +618,8 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     off = align_up(off + (size_t)n * k * 4);
     P->ws_xlow = off;
     off = align_up(off + (size_t)n * k * 2);
+    P->ws_xsc = off;                          // per-block max bits and inverse scales
+    off = align_up(off + (size_t)m * 8);
     P->ws_part = off;
     off = align_up(off + 2 * kNormBlocks * 8);
     P->ws_norm = off;

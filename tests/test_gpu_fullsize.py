@@ -171,7 +171,8 @@ def test_n8192_k8192_blockings(torch, T, n0, flags):
     assert err <= TOL64
 
 
-def test_mixed_hard_n16384_k16384(torch, T):
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_mixed_hard_n16384_k16384(torch, T, prec):
     # cond(L) ~ 1e6: the refined solve must reach binary64 backward stability;
     # forward agreement with the oracle is bounded by cond(L) u, not 1e-12
     n = k = 16384
@@ -179,15 +180,16 @@ def test_mixed_hard_n16384_k16384(torch, T):
     B = gen.rhs(n, k, 6)
     cols = sample_cols(k, 106)
     info = T.Info()
-    Xs, X = gpu_solve_cols(torch, T, Ld, torch.from_numpy(B).cuda(), "bf16", info=info,
+    Xs, X = gpu_solve_cols(torch, T, Ld, torch.from_numpy(B).cuda(), prec, info=info,
                            cols=cols)
+    assert bool(torch.isfinite(X).all())
     L = Ld.cpu().numpy()
     del Ld, X
     torch.cuda.empty_cache()
     Bs = np.ascontiguousarray(B[:, cols])
     berr = oracle.backward_err(L, Xs, Bs)
     berr_or = oracle.backward_err(L, oracle.trsm(L, Bs), Bs)
-    log(f"hard bf16 full size: {info.iterations} corrections, converged={info.converged}, "
+    log(f"hard {prec} full size: {info.iterations} corrections, converged={info.converged}, "
         f"sampled backward error {berr:.2e} (oracle's own {berr_or:.2e})")
     if info.converged:
         assert berr <= 1e-14
