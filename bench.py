@@ -262,12 +262,14 @@ def run_suite(args, torch, T, gen, dev):
     L64 = gen.chol_lower_on(torch, dev, n, args.seed)
     for k in (128, 2048, 32768):
         B64 = torch.from_numpy(gen.rhs(n, k, args.seed)).to(dev)
-        for prec in ("f64", "f32"):
+        for prec, n0 in [(p_, n0_) for p_ in ("f64", "f32")
+                         for n0_ in ((0, 256, 512) if k == 128 else (0,))]:
             es = 4 if prec == "f32" else 8
-            ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, 0, 0, 3)
+            ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, n0, 0, 3)
             tf = float(n) * n * k / (ms * 1e-3) / 1e12
             alg_bytes = es * (n * (n + 1) / 2 + 2 * n * k)
             emit({"suite": "nk_sweep", "n": n, "k": k, "precision": prec, "n0": int(info.n0),
+                  "auto": n0 == 0,
                   "n0_paper_rule": int(info.n0_paper_rule), "ms": round(ms, 3),
                   "tflops_n2k": round(tf, 2), "frac_peak": round(tf / PEAK[prec], 4),
                   "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1)})

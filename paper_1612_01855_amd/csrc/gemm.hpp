@@ -35,6 +35,7 @@
 
 #include "common.hpp"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace trsm {
@@ -57,6 +58,9 @@ struct GemmParams {
   TC2* C2; int64_t ldc2;
   const float* rscale; int64_t ld_rs;
   const float* ascale;        // if set, alpha is multiplied by *ascale (device value)
+  void* part;                 // split-K scratch (element type Mfma<TIn>::Acc), or null
+  int64_t part_bytes;         // its size; the launcher picks ksplit to fit
+  int ksplit;                 // set by the launcher: K slices (<= 1: no split)
   int M, N, K;
   int zdiv;
   double alpha, beta;
@@ -133,29 +137,75 @@ __device__ __forceinline__ int chunk_range(int K, uint32_t flags, int r0, int c0
   return kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 }
 
+// Split-K: slice s of S covers the global chunks [s*cps, (s+1)*cps) of K,
+// intersected with the tile's own range.
+template <int BK>
+__device__ __forceinline__ int split_range(int K, int s, int S, int nchunks, int& kbeg) {
+  if (S <= 1) return nchunks;
+  const int nck = (K + BK - 1) / BK, cps = (nck + S - 1) / S;
+  const int lo = max(s * cps, kbeg / BK), hi = min((s + 1) * cps, kbeg / BK + nchunks);
+  kbeg = lo * BK;
+  return hi > lo ? hi - lo : 0;
+}
+
+template <typename TIn, typename TCin, typename TCout>
+using EpiType = typename std::conditional<std::is_same<TCout, double>::value ||
+                                              std::is_same<TCin, double>::value,
+                                          double, typename Mfma<TIn>::Acc>::type;
+
+// One output element: Cout = beta*Cin + alpha*rs*v (+ second output).
+template <typename TIn, typename TCin, typename TCout, typename TC2, typename Epi>
+__device__ __forceinline__ void epi_store(const GemmParams<TIn, TCin, TCout, TC2>& p,
+                                          TCout* __restrict__ Co, const TCin* __restrict__ Ci,
+                                          int row, int col, Epi v, Epi alpha, Epi beta,
+                                          bool use_beta, Epi rs) {
+  v = alpha * (v * rs);
+  if (use_beta) v += beta * static_cast<Epi>(Ci[(int64_t)row * p.ldci + col]);
+  Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
+  if (p.C2) {
+    const TC2 w = cvt<TC2>(v * static_cast<Epi>(p.c2scale));
+    if (p.flags & G_C2_T) p.C2[(int64_t)col * p.ldc2 + row] = w;
+    else p.C2[(int64_t)row * p.ldc2 + col] = w;
+  }
+}
+
 // Epilogue: Cout = beta*Cin + alpha*rowscale*acc (+ optional second output).
 // Lane (gi, g) holds column gi and rows out_row(g, r) of every 16x16 tile.
 template <typename TIn, typename TCin, typename TCout, typename TC2, int TM, int TN, int WTM,
           int WTN>
 __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout, TC2>& p,
                                               const typename Mfma<TIn>::Out (&acc)[TM][TN],
-                                              int zo, int zi, int r0, int c0, int wm, int wn,
-                                              int g, int gi) {
+                                              int zo, int zi, int z, int s, int r0, int c0,
+                                              int wm, int wn, int g, int gi) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
+  const int M = p.M, N = p.N;
+  if (p.ksplit > 1) {
+    // split-K: raw partial sums, summed and finished by gemm_splitk_finish
+    Acc* __restrict__ P = static_cast<Acc*>(p.part) + ((int64_t)z * p.ksplit + s) * M * N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wm * WTM + i * 16 + MF::out_row(g, r);
+        if (row >= M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int col = c0 + wn * WTN + j * 16 + gi;
+          if (col < N) P[(int64_t)row * N + col] = acc[i][j][r];
+        }
+      }
+    return;
+  }
   TCout* __restrict__ Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
   const TCin* __restrict__ Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
   const bool use_beta = (p.flags & G_BETA) && Ci;
   const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
-  const bool c2t = p.flags & G_C2_T;
   // the epilogue runs in binary64 whenever C is binary64 on either side
-  using Epi = typename std::conditional<std::is_same<TCout, double>::value ||
-                                            std::is_same<TCin, double>::value,
-                                        double, Acc>::type;
+  using Epi = EpiType<TIn, TCin, TCout>;
   Epi alpha = static_cast<Epi>(p.alpha);
   if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
   const Epi beta = static_cast<Epi>(p.beta);
-  const int M = p.M, N = p.N;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -168,14 +218,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout,
       for (int j = 0; j < TN; ++j) {
         const int col = c0 + wn * WTN + j * 16 + gi;
         if (col >= N) continue;
-        Epi v = alpha * (static_cast<Epi>(acc[i][j][r]) * rs);
-        if (use_beta) v += beta * static_cast<Epi>(Ci[(int64_t)row * p.ldci + col]);
-        Co[(int64_t)row * p.ldco + col] = static_cast<TCout>(v);
-        if (p.C2) {
-          const TC2 w = cvt<TC2>(v * static_cast<Epi>(p.c2scale));
-          if (c2t) p.C2[(int64_t)col * p.ldc2 + row] = w;
-          else p.C2[(int64_t)row * p.ldc2 + col] = w;
-        }
+        epi_store(p, Co, Ci, row, col, static_cast<Epi>(acc[i][j][r]), alpha, beta, use_beta, rs);
       }
     }
   }
@@ -202,7 +245,7 @@ constexpr int vmcnt_imm(int n) {
 template <typename TIn, typename TCin, typename TCout, typename TC2, int BM, int BN, int WGM,
           int WGN>
 __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
-                                              const int r0, const int c0) {
+                                              int s, const int r0, const int c0) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
   using Out = typename MF::Out;
@@ -235,7 +278,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
   const int M = p.M, N = p.N, K = p.K;
   const int lda = (int)p.lda, ldb = (int)p.ldb;
   int kbeg;
-  const int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
+  int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
+  nchunks = split_range<BK>(K, s, p.ksplit, nchunks, kbeg);
   const bool a_lower = p.flags & G_A_LOWER;
   const bool b_lower = p.flags & G_B_LOWER;
 
@@ -326,7 +370,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
           for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[i][e], fb[e][j], acc[i][j]);
     }
   }
-  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, r0, c0, wm, wn, g, gi);
+  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, z, s, r0, c0, wm, wn, g,
+                                                        gi);
 }
 
 // Register-staged tile: every operand layout and alignment (the general
@@ -334,7 +379,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
 template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
 __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCout, TC2>& p,
-                                                 int z, const int r0, const int c0) {
+                                                 int z, int s, const int r0, const int c0) {
   using MF = Mfma<TIn>;
   using Acc = typename MF::Acc;
   using Out = typename MF::Out;
@@ -377,7 +422,8 @@ __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCo
   const bool a_lower = p.flags & G_A_LOWER;
   const bool b_lower = p.flags & G_B_LOWER;
   int kbeg;
-  const int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
+  int nchunks = chunk_range<BM, BK>(K, p.flags, r0, c0, kbeg);
+  nchunks = split_range<BK>(K, s, p.ksplit, nchunks, kbeg);
 
   Out acc[TM][TN];
 #pragma unroll
@@ -526,7 +572,8 @@ __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCo
     }
   }
 
-  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, r0, c0, wm, wn, g, gi);
+  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, z, s, r0, c0, wm, wn, g,
+                                                        gi);
 }
 
 
@@ -536,7 +583,7 @@ template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
           int GROUP_M = 8, bool XCD_REMAP = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
-                                          int bid, int nwg) {
+                                          int s, int bid, int nwg) {
   const int ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
   const bool fold = tri_fold(p.M, p.K, p.flags, BM);
   const bool uniform = fold || !(p.flags & (G_A_LOWER | G_B_LOWER));
@@ -545,9 +592,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
   tile_slot<GROUP_M, XCD_REMAP>(rows, ntn, uniform, bid, nwg, slot, tn);
   auto one = [&](int tm) {
     if constexpr (ALIGNED && !BKMAJOR && Mfma<TIn>::kPerLane == 1)
-      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, tm * BM, tn * BN);
+      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, s, tm * BM, tn * BN);
     else
-      gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, tm * BM,
+      gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, s, tm * BM,
                                                                                tn * BN);
   };
   one(slot);
@@ -561,8 +608,38 @@ template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
 __global__ __launch_bounds__(WGM * WGN * 64, 2)
 void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
-  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, blockIdx.z, blockIdx.x,
-                                                                      gridDim.x);
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, blockIdx.z, blockIdx.y,
+                                                                      blockIdx.x, gridDim.x);
+}
+
+// Split-K finish: the fixed-order sum of the ksplit partial products of
+// every element, then the usual epilogue (deterministic: the order of the
+// sum never depends on scheduling).
+template <typename TIn, typename TCin, typename TCout, typename TC2>
+__global__ __launch_bounds__(256) void gemm_splitk_finish(GemmParams<TIn, TCin, TCout, TC2> p,
+                                                          int batch) {
+  using Acc = typename Mfma<TIn>::Acc;
+  using Epi = EpiType<TIn, TCin, TCout>;
+  const int64_t MN = (int64_t)p.M * p.N, total = MN * batch;
+  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
+  Epi alpha = static_cast<Epi>(p.alpha);
+  if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
+  const Epi beta = static_cast<Epi>(p.beta);
+  const Acc* __restrict__ P = static_cast<const Acc*>(p.part);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int z = (int)(e / MN);
+    const int64_t rc = e - z * MN;
+    const int row = (int)(rc / p.N), col = (int)(rc - (int64_t)row * p.N);
+    const Acc* q = P + (int64_t)z * p.ksplit * MN + rc;
+    Acc v = q[0];
+    for (int t = 1; t < p.ksplit; ++t) v += q[t * MN];
+    const int zo = z / p.zdiv, zi = z % p.zdiv;
+    TCout* Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
+    const TCin* Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
+    const Epi rs = use_rs ? static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]) : Epi(1);
+    epi_store(p, Co, Ci, row, col, static_cast<Epi>(v), alpha, beta, (p.flags & G_BETA) && Ci, rs);
+  }
 }
 
 // Grouped launch: many independent products of one element type in one
@@ -583,7 +660,7 @@ void gemm_grouped_kernel(const GemmParams<TIn, TCin, TCout, TC2>* __restrict__ e
   const GemmParams<TIn, TCin, TCout, TC2>& p = entries[lo];
   const int tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
   const int local = b - tile_start[lo];
-  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, local / tiles,
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, local / tiles, 0,
                                                                       local % tiles, tiles);
 }
 
@@ -600,6 +677,26 @@ inline bool gemm_aligned(const P& p) {
          (BKMAJOR || p.N % VEC == 0) && span_a < kBufOOB && span_b < kBufOOB;
 }
 
+// Split-K policy: products with at most half a round of workgroups split K
+// into S slices (each at least kSplitMinChunks chunks) so that at most one
+// round runs (kSplitTarget = two 128 x 128 workgroups per compute unit), as
+// far as the scratch in p.part holds the partial products.  Without scratch
+// (p.part null) nothing is split.
+constexpr int kSplitTarget = 512;
+constexpr int kSplitMinChunks = 4;
+constexpr int kSplitMax = 16;
+template <typename TIn, typename P>
+inline int gemm_ksplit(const P& p, int64_t wgs, int batch, int target) {
+  if (!p.part || 2 * wgs > target) return 1;
+  constexpr int BK = 128 / sizeof(TIn);
+  const int64_t nck = (p.K + BK - 1) / BK;
+  int64_t S = std::min<int64_t>(target / wgs, nck / kSplitMinChunks);
+  S = std::min<int64_t>(S, kSplitMax);
+  const int64_t per = (int64_t)p.M * p.N * batch * (int64_t)sizeof(typename Mfma<TIn>::Acc);
+  if (per > 0) S = std::min<int64_t>(S, p.part_bytes / per);
+  return S > 1 ? (int)S : 1;
+}
+
 // Host-side launch helper.  Picks the aligned (16-byte vector) path when every
 // operand start, leading dimension and batch stride allows it.
 template <typename TIn, typename TCin, typename TCout, typename TC2,
@@ -609,12 +706,22 @@ inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int ba
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
   const bool aligned = gemm_aligned<TIn, BM, BN, BKMAJOR>(p);
   const int64_t tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
-  dim3 grid((unsigned)tiles, 1, (unsigned)batch);
+  GemmParams<TIn, TCin, TCout, TC2> q = p;
+  // one round of workgroups: two per compute unit for the 128 x 128 tiles,
+  // four for the smaller ones (their registers and LDS allow it)
+  const int target = (BM * BN >= 128 * 128) ? kSplitTarget : 2 * kSplitTarget;
+  q.ksplit = gemm_ksplit<TIn>(p, tiles * batch, batch, target);
+  dim3 grid((unsigned)tiles, (unsigned)q.ksplit, (unsigned)batch);
   dim3 block(WGM * WGN * 64);
   if (aligned)
-    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, true><<<grid, block, 0, stream>>>(p);
+    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, true><<<grid, block, 0, stream>>>(q);
   else
-    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, false><<<grid, block, 0, stream>>>(p);
+    gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, false><<<grid, block, 0, stream>>>(q);
+  if (q.ksplit > 1) {
+    const int64_t total = (int64_t)p.M * p.N * batch;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    gemm_splitk_finish<TIn, TCin, TCout, TC2><<<g, 256, 0, stream>>>(q, batch);
+  }
   return hipGetLastError();
 }
 

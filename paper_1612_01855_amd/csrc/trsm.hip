@@ -120,6 +120,36 @@ struct TimerScope {
   ~TimerScope() { g_timer = prev; }
 };
 
+// Split-K scratch for the products launched inside one library call (the
+// caller's workspace, or the plan's own buffer during the inversion).
+struct SplitBuf {
+  void* ptr = nullptr;
+  int64_t bytes = 0;
+};
+thread_local SplitBuf g_split;
+
+struct SplitScope {
+  SplitBuf prev;
+  SplitScope(void* p, int64_t b) : prev(g_split) { g_split = SplitBuf{p, b}; }
+  ~SplitScope() { g_split = prev; }
+};
+
+template <typename P>
+void use_split(P& p) {
+  if (!p.part) {
+    p.part = g_split.ptr;
+    p.part_bytes = g_split.bytes;
+  }
+}
+
+// Scratch for split-K partial products: up to kSplitMax slices of an
+// output of `elems` elements (binary64 partials), at most 128 MiB.
+constexpr size_t kSplitCap = (size_t)128 << 20;
+size_t split_bytes(int64_t elems) {
+  const size_t want = (size_t)kSplitMax * (size_t)std::max<int64_t>(elems, 0) * 8;
+  return std::min(want, kSplitCap);
+}
+
 template <typename F>
 hipError_t timed(double flops, hipStream_t s, F&& launch) {
   LaunchTimer* t = g_timer;
@@ -154,8 +184,11 @@ struct trsm_plan_s {
   // workspace layout (byte offsets)
   size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_xsc = 0, ws_part = 0,
          ws_norm = 0;
+  size_t ws_split = 0, ws_split_bytes = 0;
   size_t ws_bytes = 0;
   unsigned long long* d_bad = nullptr;   // first singular row (device word)
+  void* d_split = nullptr;               // split-K scratch of the inversion
+  size_t inv_split_bytes = 0;
   LaunchTimer timer;
   // lookahead: a second stream and the events that order the two
   hipStream_t side = nullptr;
@@ -214,9 +247,18 @@ namespace {
 template <typename T>
 struct Gemm {
   using P = GemmParams<T, T, T, float>;
-  static hipError_t run(const P& p, int batch, hipStream_t s) {
-    return timed(gemm_flops(p, batch), s,
-                 [&] { return launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s); });
+  // Products that give fewer workgroups than two per compute unit with
+  // 128 x 128 tiles use 64 x 64 tiles (four times as many workgroups; the
+  // binary64/binary32 matrix-core rate per workgroup does not depend on the
+  // tile), and split K if they are still small.
+  static hipError_t run(const P& p0, int batch, hipStream_t s) {
+    P p = p0;
+    use_split(p);
+    const bool small = (int64_t)gemm_wgs(p.M, p.N, p.K, p.flags, 128, 128) * batch < kSplitTarget;
+    return timed(gemm_flops(p, batch), s, [&] {
+      return small ? launch_gemm<T, T, T, float, 64, 64, 2, 2, false>(p, batch, s)
+                   : launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s);
+    });
   }
 };
 
@@ -326,6 +368,8 @@ trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, 
   hipEvent_t ev_start = look ? P.events[2 * m] : nullptr;
   hipEvent_t ev_end = look ? P.events[2 * m + 1] : nullptr;
   hipStream_t s2 = P.side;
+  // the two streams' products may run at once: no shared split-K scratch
+  SplitScope no_split(look ? nullptr : g_split.ptr, look ? 0 : g_split.bytes);
   if (look) {
     TRSM_HIP(hipEventRecord(ev_start, s));
     TRSM_HIP(hipStreamWaitEvent(s2, ev_start, 0));
@@ -415,6 +459,7 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.Cout = D + r0 * k; p.ldco = k;
       p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
       p.flags = G_A_LOWER | G_A_ZERO_UPPER;
+      use_split(p);
       TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
         return launch_gemm<float, float, float, float, 128, 128, 2, 2, false>(p, 1, s);
       }));
@@ -434,6 +479,7 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       p.M = (int)rows; p.N = (int)k; p.K = (int)sz;
       p.alpha = -1.0; p.beta = 1.0;
       p.flags = G_BETA | G_ROWSCALE;
+      use_split(p);
       TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
         return launch_gemm<TL, float, float, float, 128, 128, 2, 2, true>(p, 1, s);
       }));
@@ -625,7 +671,12 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     P->ws_norm = off;
     off = align_up(off + 8 * 8);
   }
+  P->ws_split = off;
+  P->ws_split_bytes = split_bytes(n * k);
+  off = align_up(off + P->ws_split_bytes);
   P->ws_bytes = off;
+  // inversion levels: batch x h x h outputs, at most n * n0 / 4 elements
+  P->inv_split_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : split_bytes(n * n0 / 4);
   *out = P;
   return TRSM_OK;
 }
@@ -650,6 +701,7 @@ trsm_status trsm_plan_get_info(trsm_plan_t P, trsm_plan_info* info) {
 trsm_status trsm_plan_destroy(trsm_plan_t P) {
   if (!P) return TRSM_OK;
   if (P->d_bad) (void)hipFree(P->d_bad);
+  if (P->d_split) (void)hipFree(P->d_split);
   P->timer.release();
   for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
   if (P->side) (void)hipStreamDestroy(P->side);
@@ -675,6 +727,13 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
       return TRSM_ENOMEM;
     }
   }
+  if (!P->d_split && P->inv_split_bytes && P->leaf < n0) {
+    if (hipMalloc(&P->d_split, P->inv_split_bytes) != hipSuccess) {
+      P->d_split = nullptr;
+      return TRSM_ENOMEM;
+    }
+  }
+  SplitScope split_scope(P->d_split, P->d_split ? (int64_t)P->inv_split_bytes : 0);
   TRSM_HIP(hipMemsetAsync(P->d_bad, 0xFF, sizeof(unsigned long long), s));
   if (P->prec == TRSM_F32)
     TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s));
@@ -745,6 +804,7 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   TimerScope timer_scope(&P->timer);
   const char* lb = (const char*)Linv;
   char* ws = (char*)workspace;
+  SplitScope split_scope(ws + P->ws_split, (int64_t)P->ws_split_bytes);
   if (rec) {
     if (P->prec == TRSM_F64) {
       if (X != B) TRSM_HIP(launch_copy2d<double, double>((const double*)B, ldb, (double*)X, ldx, n, k, 1.0, s));
@@ -771,9 +831,8 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
 }
 
 size_t trsm_residual_workspace_bytes(int64_t n, int64_t k) {
-  (void)n;
-  (void)k;
-  return align_up(2 * kNormBlocks * 8) + align_up(8 * 8);
+  if (n < 0 || k < 0) return 0;
+  return align_up(2 * kNormBlocks * 8) + align_up(8 * 8) + align_up(split_bytes(n * k));
 }
 
 trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl, const double* X,
@@ -792,6 +851,8 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl, co
   hipStream_t s = (hipStream_t)stream;
   double* part = (double*)workspace;
   double* dn = (double*)((char*)workspace + align_up(2 * kNormBlocks * 8));
+  SplitScope split_scope((char*)workspace + align_up(2 * kNormBlocks * 8) + align_up(8 * 8),
+                         (int64_t)split_bytes(n * k));
   TRSM_HIP(gemm_simple<double>(L, ldl, X, ldx, B, ldb, R, ldr, n, k, n, -1.0, 1.0, G_A_LOWER, s));
   TRSM_HIP(launch_sumsq_max(R, ldr, n, k, part, dn, s));
   TRSM_HIP(launch_sumsq_max(X, ldx, n, k, part, dn + 2, s));
