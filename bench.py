@@ -63,7 +63,7 @@ def cpu_baseline(L, B, seconds_hint: float = 15.0):
     """Time the oracle on the first columns of the same B (column sample)."""
     import oracle
     threads = oracle.max_threads()
-    k_s = min(B.shape[1], 64 * threads)
+    k_s = min(B.shape[1], 128 * threads)
     n = L.shape[0]
     t0 = time.perf_counter()
     oracle.trsm(L, B[:, :k_s])
