@@ -224,6 +224,81 @@ __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout,
   }
 }
 
+// Epilogue for products computed with the MFMA operands swapped (the tile of
+// C^T is accumulated): lane (gi, g) then holds row gi and the four adjacent
+// columns 4g..4g+3 of every 16x16 tile, so binary32 C moves in 16-byte
+// vectors.
+template <typename TIn, typename TCin, typename TCout, typename TC2, int TM, int TN, int WTM,
+          int WTN>
+__device__ __forceinline__ void gemm_epilogue_t(const GemmParams<TIn, TCin, TCout, TC2>& p,
+                                                const typename Mfma<TIn>::Out (&acc)[TM][TN],
+                                                int zo, int zi, int z, int s, int r0, int c0,
+                                                int wm, int wn, int g, int gi) {
+  using MF = Mfma<TIn>;
+  using Acc = typename MF::Acc;
+  const int M = p.M, N = p.N;
+  if (p.ksplit > 1) {
+    Acc* __restrict__ P = static_cast<Acc*>(p.part) + ((int64_t)z * p.ksplit + s) * M * N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = r0 + wm * WTM + i * 16 + gi;
+      if (row >= M) continue;
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = c0 + wn * WTN + j * 16 + 4 * g + r;
+          if (col < N) P[(int64_t)row * N + col] = acc[i][j][r];
+        }
+    }
+    return;
+  }
+  TCout* __restrict__ Co = p.Cout + zo * p.sco_o + zi * p.sco_i;
+  const TCin* __restrict__ Ci = p.Cin ? p.Cin + zo * p.sci_o + zi * p.sci_i : nullptr;
+  const bool use_beta = (p.flags & G_BETA) && Ci;
+  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
+  using Epi = EpiType<TIn, TCin, TCout>;
+  Epi alpha = static_cast<Epi>(p.alpha);
+  if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
+  const Epi beta = static_cast<Epi>(p.beta);
+  constexpr bool F32C = std::is_same<TCout, float>::value && std::is_same<TCin, float>::value;
+  const bool vec = F32C && !p.C2 &&
+                   (((uintptr_t)Co | (uintptr_t)(Ci ? Ci : Co) | (uintptr_t)(p.ldco * 4) |
+                     (uintptr_t)(p.ldci * 4)) & 15) == 0;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int row = r0 + wm * WTM + i * 16 + gi;
+    if (row >= M) continue;
+    const Epi rs = use_rs ? static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]) : Epi(1);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col0 = c0 + wn * WTN + j * 16 + 4 * g;
+      if constexpr (F32C) {
+        if (vec && col0 + 3 < N) {
+          typedef float F4 __attribute__((ext_vector_type(4)));
+          F4 cin = {0.f, 0.f, 0.f, 0.f};
+          if (use_beta) cin = *reinterpret_cast<const F4*>(Ci + (int64_t)row * p.ldci + col0);
+          F4 o;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            Epi v = alpha * (static_cast<Epi>(acc[i][j][r]) * rs);
+            if (use_beta) v += beta * static_cast<Epi>(cin[r]);
+            o[r] = static_cast<float>(v);
+          }
+          *reinterpret_cast<F4*>(Co + (int64_t)row * p.ldco + col0) = o;
+          continue;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = col0 + r;
+        if (col < N)
+          epi_store(p, Co, Ci, row, col, static_cast<Epi>(acc[i][j][r]), alpha, beta, use_beta, rs);
+      }
+    }
+  }
+}
+
 // s_waitcnt immediate that waits for at most n outstanding vector-memory
 // operations and nothing else (gfx9 encoding).
 constexpr int vmcnt_imm(int n) {
@@ -402,6 +477,10 @@ __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCo
   static_assert(A_ITERS * NT == BM * VPR, "A tile load must divide evenly");
   static_assert(B_ITERS * NT == (BKMAJOR ? BN * VPR : BK * (BN / VEC)), "B tile load must divide evenly");
   static_assert(BKMAJOR || MF::kPerLane == 1, "row-major B needs a one-k-per-lane instruction");
+  // With both operands k-contiguous the MFMA can take them in either order;
+  // taking B first accumulates the tile of C^T, whose lane layout lets the
+  // epilogue move binary32 C in 16-byte vectors.
+  constexpr bool SWAP = BKMAJOR && (MF::kPerLane > 1) && std::is_same<Acc, float>::value;
 
   __shared__ __attribute__((aligned(16))) TIn As[2][BM * LDA_S];
   __shared__ __attribute__((aligned(16))) TIn Bs[2][B_ELEMS];
@@ -565,15 +644,20 @@ __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCo
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[i], fb[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = SWAP ? MF::mma(fb[j], fa[i], acc[i][j]) : MF::mma(fa[i], fb[j], acc[i][j]);
       }
       if (more) store_ab(buf ^ 1, kbeg + (c + 1) * BK);
       __syncthreads();
     }
   }
 
-  gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, z, s, r0, c0, wm, wn, g,
-                                                        gi);
+  if constexpr (SWAP)
+    gemm_epilogue_t<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, z, s, r0, c0, wm, wn,
+                                                            g, gi);
+  else
+    gemm_epilogue<TIn, TCin, TCout, TC2, TM, TN, WTM, WTN>(p, acc, zo, zi, z, s, r0, c0, wm, wn, g,
+                                                          gi);
 }
 
 
