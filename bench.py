@@ -286,7 +286,7 @@ def run_suite(args, torch, T, gen, dev):
     B64 = torch.from_numpy(gen.rhs(n, k, args.seed)).to(dev)
     ms64, _, X64 = time_solves(T, torch, dev, L64, B64, "f64", 0, 0, 3)
     nx = torch.linalg.norm(X64).item()
-    for prec in ("bf16", "f16"):
+    for prec in ("bf16", "f16", "fp8"):
         s = T.Solver.create(n, k, prec, 0, 0, device=dev)
         X = torch.empty_like(B64)
         inf = T.Info()
@@ -443,7 +443,7 @@ def main():
 
     mixed = {}
     if not args.no_mixed and args.precision == "f64":
-        for prec in ("bf16", "f16"):
+        for prec in ("bf16", "f16", "fp8"):
             try:
                 s2 = T.Solver.create(n, k, prec, args.n0, 0, device=dev)
                 Xm = torch.empty_like(Bd)

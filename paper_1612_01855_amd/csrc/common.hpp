@@ -15,6 +15,10 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 typedef __bf16 bf16_t;
 typedef _Float16 f16_t;
+// 8-bit float (e4m3: 4 exponent bits, 3 mantissa bits) held as its bit
+// pattern; produced by the hardware conversion and consumed by the 8-bit
+// matrix-core instruction, which use the same encoding.
+typedef uint8_t fp8_t;
 
 constexpr int kWave = 64;
 
@@ -74,8 +78,26 @@ template <> struct Mfma<f16_t> {
   static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
 };
 
+template <> struct Mfma<fp8_t> {
+  using Acc = float;
+  using Frag = long;   // eight 8-bit values
+  using Out = f4;
+  static constexpr int kPerLane = 8;
+  static __device__ __forceinline__ Out mma(Frag a, Frag b, Out c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
+};
+
 template <typename To, typename From>
 __device__ __forceinline__ To cvt(From v) { return static_cast<To>(v); }
+// round to nearest e4m3 (saturating conversion of the hardware)
+template <> __device__ __forceinline__ fp8_t cvt<fp8_t, float>(float v) {
+  return (fp8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
+}
+template <> __device__ __forceinline__ fp8_t cvt<fp8_t, double>(double v) {
+  return cvt<fp8_t, float>(static_cast<float>(v));
+}
 template <> __device__ __forceinline__ bf16_t cvt<bf16_t, float>(float v) { return static_cast<bf16_t>(v); }
 template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double v) { return static_cast<bf16_t>(static_cast<float>(v)); }
 template <> __device__ __forceinline__ f16_t cvt<f16_t, double>(double v) { return static_cast<f16_t>(static_cast<float>(v)); }

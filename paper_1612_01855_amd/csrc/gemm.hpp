@@ -73,6 +73,7 @@ template <> struct VecOf<double> { typedef double T2 __attribute__((ext_vector_t
 template <> struct VecOf<float> { typedef float T2 __attribute__((ext_vector_type(4))); };
 template <> struct VecOf<bf16_t> { typedef __bf16 T2 __attribute__((ext_vector_type(8))); };
 template <> struct VecOf<f16_t> { typedef _Float16 T2 __attribute__((ext_vector_type(8))); };
+template <> struct VecOf<fp8_t> { typedef uint8_t T2 __attribute__((ext_vector_type(16))); };
 
 // Buffer descriptor word 3 for the gfx9 family (raw, untyped loads).
 constexpr int kBufWord3 = 0x00020000;

@@ -368,6 +368,8 @@ template hipError_t launch_lowcopy<bf16_t>(const double*, int64_t, int64_t, int6
                                            bf16_t*, float*, float, hipStream_t);
 template hipError_t launch_lowcopy<f16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
                                           f16_t*, float*, float, hipStream_t);
+template hipError_t launch_lowcopy<fp8_t>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                          fp8_t*, float*, float, hipStream_t);
 
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -387,6 +389,8 @@ hipError_t launch_lowx(const float* D, int64_t ldd, int64_t rows, int64_t cols, 
 template hipError_t launch_lowx<bf16_t>(const float*, int64_t, int64_t, int64_t, bf16_t*, int64_t,
                                         unsigned*, float*, int, hipStream_t);
 template hipError_t launch_lowx<f16_t>(const float*, int64_t, int64_t, int64_t, f16_t*, int64_t,
+                                       unsigned*, float*, int, hipStream_t);
+template hipError_t launch_lowx<fp8_t>(const float*, int64_t, int64_t, int64_t, fp8_t*, int64_t,
                                        unsigned*, float*, int, hipStream_t);
 
 template <typename T>

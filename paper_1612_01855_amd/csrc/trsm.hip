@@ -71,7 +71,9 @@ inline int64_t prev_pow2(int64_t v) {
 }
 
 inline size_t elem_size(trsm_precision p) { return p == TRSM_F32 ? 4 : 8; }
-inline bool is_mixed(trsm_precision p) { return p == TRSM_MIXED_BF16 || p == TRSM_MIXED_F16; }
+inline bool is_mixed(trsm_precision p) {
+  return p == TRSM_MIXED_BF16 || p == TRSM_MIXED_F16 || p == TRSM_MIXED_FP8;
+}
 
 }  // namespace
 
@@ -446,7 +448,9 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
   const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
   // largest magnitude of a solved block -> [2^etarget, 2^(etarget+1)) in the
   // low copy: half keeps headroom below its largest finite value (65504)
-  const int etarget = std::is_same<TL, f16_t>::value ? 14 : 0;
+  // (e4m3's largest finite value is 448 or 240 depending on the encoding:
+  // keep the block maximum below 128)
+  const int etarget = std::is_same<TL, f16_t>::value ? 14 : std::is_same<TL, fp8_t>::value ? 6 : 0;
   TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
   TRSM_HIP(launch_fill_u32(amax, m, 0u, s));
   for (int64_t i = 0; i < m; ++i) {
@@ -751,6 +755,9 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
     if (P->prec == TRSM_MIXED_BF16)
       TRSM_HIP(launch_lowcopy<bf16_t>((const double*)L, ldl, n, n0, m, (bf16_t*)(base + P->off_llow),
                                       rs, 1.0f, s));
+    else if (P->prec == TRSM_MIXED_FP8)
+      TRSM_HIP(launch_lowcopy<fp8_t>((const double*)L, ldl, n, n0, m, (fp8_t*)(base + P->off_llow),
+                                     rs, 128.0f, s));
     else
       TRSM_HIP(launch_lowcopy<f16_t>((const double*)L, ldl, n, n0, m, (f16_t*)(base + P->off_llow),
                                      rs, 16384.0f, s));
@@ -823,6 +830,9 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
     case TRSM_MIXED_BF16:
       return solve_mixed<bf16_t>(*P, (const double*)L, ldl, lb, (const double*)B, ldb, (double*)X,
                                  ldx, ws, s, info);
+    case TRSM_MIXED_FP8:
+      return solve_mixed<fp8_t>(*P, (const double*)L, ldl, lb, (const double*)B, ldb, (double*)X,
+                                ldx, ws, s, info);
     case TRSM_MIXED_F16:
       return solve_mixed<f16_t>(*P, (const double*)L, ldl, lb, (const double*)B, ldb, (double*)X,
                                 ldx, ws, s, info);

@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(HERE, "libtrsm.so")
 # trsm_status
 OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENOTCONVERGED, EBUSY = range(7)
 # trsm_precision
-F64, F32, MIXED_BF16, MIXED_F16 = range(4)
-PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16}
+F64, F32, MIXED_BF16, MIXED_F16, MIXED_FP8 = range(5)
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16, "fp8": MIXED_FP8}
 # plan flags
 FLAG_NO_REFINE = 0x1
 FLAG_RECURSIVE = 0x2

@@ -88,6 +88,18 @@ def test_plan_layout(T, n, k, n0):
         T.trsm_plan_destroy(p)
 
 
+def test_fp8_plan_is_a_mixed_plan(T):
+    p = T.trsm_plan(300, 20, T.MIXED_FP8, 64, 0)
+    try:
+        i = T.trsm_plan_get_info(p)
+        assert i.precision == T.MIXED_FP8 and i.n0 == 64
+        assert i.linv_bytes >= 5 * 64 * 64 * 12 + 300 * 300
+    finally:
+        T.trsm_plan_destroy(p)
+    with pytest.raises(T.TrsmError):
+        T.trsm_plan(300, 20, T.MIXED_FP8, 64, T.FLAG_RECURSIVE)
+
+
 def test_mixed_plan_has_low_precision_copies(T):
     p64 = T.trsm_plan(512, 64, T.F64, 128, 0)
     pb = T.trsm_plan(512, 64, T.MIXED_BF16, 128, 0)

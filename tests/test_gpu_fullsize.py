@@ -105,7 +105,7 @@ def test_f32_n16384_k16384_auto_n0(torch, T):
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
 def test_mixed_refined_n16384_k16384(torch, T, prec):
     n = k = 16384
     L, B = gen.easy_system(n, k, 2, upper=np.nan)

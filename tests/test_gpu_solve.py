@@ -233,7 +233,7 @@ def test_recursive_baseline(torch, T, prec, n, k):
 
 # ---- mixed precision with refinement ----------------------------------------------
 
-@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
 @pytest.mark.parametrize("n,k,n0", [(512, 64, 128), (1000, 40, 0)])
 def test_mixed_refined(torch, T, prec, n, k, n0):
     L, B = gen.easy_system(n, k, 51, upper=np.nan)
@@ -247,10 +247,11 @@ def test_mixed_refined(torch, T, prec, n, k, n0):
         f"(berr {info.backward_error:.1e}); unrefined {err0:.2e}")
     assert info.converged == 1
     assert err <= TOL64
-    assert err0 <= 1e-2
+    # unrefined error is reported, not pinned: only a sanity bound
+    assert err0 <= (1e-1 if prec == "fp8" else 1e-2)
 
 
-@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
 def test_mixed_hard_matrix(torch, T, prec):
     # |X| reaches ~1e5 |B| here, beyond half's range unless the low copy of
     # each solved block is rescaled
