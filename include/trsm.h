@@ -181,9 +181,15 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl,
  * (the diagonal apply of step i, the trailing update of step i) is ONE
  * grouped launch over the tiles of every system that has that phase, so the
  * whole batch takes 2*max(m_p) - 1 launches; systems with fewer blocks drop
- * out of later phases.  Each system's result is computed by the same tiles
- * in the same order as when it is solved alone, so it is bitwise independent
- * of the rest of the batch.
+ * out of later phases.  With n0 = 64 the batch instead runs as ONE
+ * persistent launch (plus a small launch that clears its counters): the
+ * left-looking form of the same sweep, X(S_i, c) = Linv_ii (B(S_i, c) -
+ * L(S_i, 0:i n0) X(0:i n0, c)), as tasks (system, step i, 64-column tile c)
+ * taken from a queue in step-major order; a task waits (on the device) for
+ * its column tile's earlier steps through a per-tile counter.  Either way
+ * each system's result is computed by the same tiles in the same order as
+ * when it is solved alone, so it is bitwise independent of the rest of the
+ * batch.
  *
  *  items[p]: n, k; L (device, lower triangle read, ldl >= n); Linv (device,
  *  filled by trsm_invert_diag with a plan of this n, the same precision and
@@ -219,6 +225,13 @@ trsm_status trsm_batch_create(int32_t count, const trsm_batch_item* items, trsm_
                               int64_t n0, trsm_batch_t* out);
 trsm_status trsm_batch_workspace_bytes(trsm_batch_t batch, size_t* bytes);
 trsm_status trsm_batch_run(trsm_batch_t batch, void* workspace, void* stream, int32_t use_graph);
+/*
+ * Blocking check of the last trsm_batch_run on `workspace` (synchronises the
+ * device): TRSM_EHIP if a dependency wait of the persistent sweep (batches
+ * made with n0 = 64) gave up, which the task order rules out, else TRSM_OK.
+ */
+trsm_status trsm_batch_check(trsm_batch_t batch, const void* workspace);
+
 trsm_status trsm_batch_destroy(trsm_batch_t batch);
 
 /*

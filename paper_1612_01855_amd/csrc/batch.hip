@@ -61,6 +61,113 @@ __global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restri
 
 constexpr int kBM = 128, kBN = 128;
 
+// Waits of the persistent sweep give up (and set the error word) after this
+// many polls of about a microsecond; by construction a wait always ends long
+// before (the awaited task was taken from the queue earlier by a running
+// workgroup).
+constexpr unsigned kSpinLimit = 1u << 22;
+
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void persist_tile(const GemmParams<T, T, T, float>& p) {
+  if constexpr (ALIGNED)
+    gemm_tile_dma<T, T, T, float, kPB, kPB, 2, 2>(p, 0, 0, 0, 0);
+  else
+    gemm_tile_staged<T, T, T, float, kPB, kPB, 2, 2, false, false>(p, 0, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ GemmParams<T, T, T, float> persist_params() {
+  GemmParams<T, T, T, float> p{};
+  p.zdiv = 1;
+  p.alpha = 1.0;
+  p.c2scale = 1.0f;
+  return p;
+}
+
+// Persistent left-looking sweep over many systems.  Workgroups take tasks
+// from a queue (an atomic head) in step-major order; a task first waits
+// until its column tile's counter shows all earlier steps done (acquire),
+// computes R(S_i, c) and X(S_i, c), and then advances the counter (release).
+// A task only ever waits for a task that was taken from the queue before it,
+// by a workgroup that is running, so every wait ends.
+template <typename T, bool ALIGNED>
+__global__ __launch_bounds__(256, 2) void persist_sweep_kernel(
+    const PersistItem<T>* __restrict__ items, const PersistTask* __restrict__ tasks, int ntasks,
+    unsigned* __restrict__ cnt, int ncnt) {
+  __shared__ int s_task;
+  unsigned* head = cnt + ncnt;
+  unsigned* err = cnt + ncnt + 1;
+  for (;;) {
+    __syncthreads();   // every thread has read s_task of the previous round
+    if (threadIdx.x == 0) s_task = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= ntasks) return;
+    const PersistTask tk = tasks[t];
+    const PersistItem<T> it = items[tk.item];
+    unsigned* mine = cnt + it.cnt + tk.ctile;
+    if (threadIdx.x == 0 && tk.step > 0) {
+      unsigned spins = 0;
+      while (__hip_atomic_load(mine, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+             (unsigned)tk.step) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    __threadfence();   // acquire for every wave: no stale X(S_j, c) in the caches
+    const int nb = it.nb;
+    const int r0 = tk.step * nb, sz = min(nb, it.n - r0);
+    const int c0 = tk.ctile * kPB, nc = min(kPB, it.k - c0);
+    {
+      // R(S_i, c) = B(S_i, c) - L(S_i, 0:r0) X(0:r0, c)
+      auto p = persist_params<T>();
+      p.A = it.L + (int64_t)r0 * it.ldl; p.lda = it.ldl;
+      p.B = it.X + c0; p.ldb = it.ldx;
+      p.Cin = it.B + (int64_t)r0 * it.ldb + c0; p.ldci = it.ldb;
+      p.Cout = it.R + (int64_t)r0 * it.ldr + c0; p.ldco = it.ldr;
+      p.M = sz; p.N = nc; p.K = r0;
+      p.alpha = -1.0; p.beta = 1.0;
+      p.flags = G_BETA;
+      persist_tile<T, ALIGNED>(p);
+    }
+    __threadfence();
+    __syncthreads();
+    {
+      // X(S_i, c) = Linv_ii R(S_i, c)
+      auto p = persist_params<T>();
+      p.A = it.Linv + (int64_t)tk.step * nb * nb; p.lda = nb;
+      p.B = it.R + (int64_t)r0 * it.ldr + c0; p.ldb = it.ldr;
+      p.Cout = it.X + (int64_t)r0 * it.ldx + c0; p.ldco = it.ldx;
+      p.M = sz; p.N = nc; p.K = sz;
+      p.flags = G_A_LOWER | G_A_ZERO_UPPER;
+      persist_tile<T, ALIGNED>(p);
+    }
+    __threadfence();   // release: X(S_i, c) is visible before the counter moves
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T>
+hipError_t launch_persist(const void* items, const void* tasks, int ntasks, unsigned* cnt,
+                          int ncnt, bool aligned, hipStream_t s) {
+  hipError_t e = launch_fill_u32(cnt, ncnt + 2, 0u, s);
+  if (e != hipSuccess || ntasks <= 0) return e;
+  const unsigned grid = (unsigned)std::min(ntasks, kPersistMaxWG);
+  const auto* it = static_cast<const PersistItem<T>*>(items);
+  const auto* tk = static_cast<const PersistTask*>(tasks);
+  if (aligned)
+    persist_sweep_kernel<T, true><<<grid, 256, 0, s>>>(it, tk, ntasks, cnt, ncnt);
+  else
+    persist_sweep_kernel<T, false><<<grid, 256, 0, s>>>(it, tk, ntasks, cnt, ncnt);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 void LaunchList::clear() {
@@ -130,9 +237,41 @@ void LaunchList::add_ew(const std::vector<EwEntry>& entries) {
   if (ph.total > 0) phases_.push_back(ph);
 }
 
+template <typename T>
+void LaunchList::add_persist(const std::vector<PersistItem<T>>& items,
+                             const std::vector<PersistTask>& tasks, unsigned* counters,
+                             int ncounters, bool aligned) {
+  Phase ph{};
+  ph.kind = std::is_same<T, double>::value ? PH_PERSIST_F64 : PH_PERSIST_F32;
+  ph.count = (int)items.size();
+  ph.ntasks = (int)tasks.size();
+  ph.total = std::min(ph.ntasks, kPersistMaxWG);
+  ph.aligned = aligned;
+  ph.counters = counters;
+  ph.ncounters = ncounters;
+  ph.entries_off = append(items.data(), items.size());
+  ph.start_off = append(tasks.data(), tasks.size());
+  if (ph.ntasks > 0) phases_.push_back(ph);
+}
+template void LaunchList::add_persist<double>(const std::vector<PersistItem<double>>&,
+                                              const std::vector<PersistTask>&, unsigned*, int, bool);
+template void LaunchList::add_persist<float>(const std::vector<PersistItem<float>>&,
+                                             const std::vector<PersistTask>&, unsigned*, int, bool);
+
 hipError_t LaunchList::run(const void* dev, hipStream_t s) const {
   const char* base = static_cast<const char*>(dev);
   for (const Phase& ph : phases_) {
+    if (ph.kind == PH_PERSIST_F64 || ph.kind == PH_PERSIST_F32) {
+      const void* items = base + ph.entries_off;
+      const void* tasks = base + ph.start_off;
+      hipError_t e = ph.kind == PH_PERSIST_F64
+                         ? launch_persist<double>(items, tasks, ph.ntasks, ph.counters,
+                                                  ph.ncounters, ph.aligned, s)
+                         : launch_persist<float>(items, tasks, ph.ntasks, ph.counters,
+                                                 ph.ncounters, ph.aligned, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const int* st = reinterpret_cast<const int*>(base + ph.start_off);
     dim3 grid((unsigned)ph.total);
     if (ph.kind == PH_GEMM_F64) {
@@ -209,6 +348,62 @@ void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items) {
 template void record_sweep<double>(LaunchList&, const std::vector<SweepItem<double>>&);
 template void record_sweep<float>(LaunchList&, const std::vector<SweepItem<float>>&);
 
+template <typename T>
+int persist_counter_words(const std::vector<SweepItem<T>>& items) {
+  int64_t c = 0;
+  for (const auto& it : items)
+    if (it.n > 0 && it.k > 0) c += ceil_div(it.k, kPB);
+  return (int)c;
+}
+template int persist_counter_words<double>(const std::vector<SweepItem<double>>&);
+template int persist_counter_words<float>(const std::vector<SweepItem<float>>&);
+
+template <typename T>
+void record_persist(LaunchList& list, const std::vector<SweepItem<T>>& items, unsigned* counters) {
+  constexpr int VEC = 16 / sizeof(T);
+  auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  std::vector<PersistItem<T>> pis;
+  std::vector<int> order;
+  bool aligned = true;
+  int cnt = 0;
+  for (const auto& it : items) {
+    if (it.n <= 0 || it.k <= 0) continue;
+    PersistItem<T> q{};
+    q.L = it.L; q.ldl = it.ldl;
+    q.Linv = it.Linv;
+    q.B = it.B; q.ldb = it.ldb;
+    q.X = it.X; q.ldx = it.ldx;
+    q.R = it.R; q.ldr = it.ldr;
+    q.n = (int)it.n; q.k = (int)it.k;
+    q.nb = (int)it.n0;
+    q.m = (int)ceil_div(it.n, it.n0);
+    q.nct = (int)ceil_div(it.k, kPB);
+    q.cnt = cnt;
+    cnt += q.nct;
+    aligned &= al(q.L) && al(q.Linv) && al(q.X) && al(q.R) && q.ldl % VEC == 0 &&
+               q.ldx % VEC == 0 && q.ldr % VEC == 0 && q.nb % VEC == 0 && q.n % VEC == 0 &&
+               q.k % VEC == 0 && (int64_t)kPB * q.ldl * (int64_t)sizeof(T) < kBufOOB &&
+               (int64_t)q.n * q.ldx * (int64_t)sizeof(T) < kBufOOB &&
+               (int64_t)q.n * q.ldr * (int64_t)sizeof(T) < kBufOOB;
+    pis.push_back(q);
+  }
+  // step-major task order, systems with more steps first within a step
+  std::vector<int> idx(pis.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return pis[a].m > pis[b].m; });
+  int max_m = 0;
+  for (const auto& q : pis) max_m = std::max(max_m, q.m);
+  std::vector<PersistTask> tasks;
+  for (int i = 0; i < max_m; ++i)
+    for (int j : idx) {
+      if (i >= pis[j].m) continue;
+      for (int c = 0; c < pis[j].nct; ++c) tasks.push_back(PersistTask{j, i, c, 0});
+    }
+  list.add_persist<T>(pis, tasks, counters, cnt, aligned);
+}
+template void record_persist<double>(LaunchList&, const std::vector<SweepItem<double>>&, unsigned*);
+template void record_persist<float>(LaunchList&, const std::vector<SweepItem<float>>&, unsigned*);
+
 }  // namespace trsm
 
 // ---------------------------------------------------------------------------
@@ -223,6 +418,7 @@ struct trsm_batch_s {
   size_t table_bytes = 0;      // upper bound, reserved at the head of the workspace
   size_t ws_bytes = 0;
   std::vector<size_t> r_off;   // offset of each item's running right-hand side
+  size_t cnt_off = 0;          // persistent sweep (n0 == kPB): its counter words
   LaunchList list;
   void* pinned = nullptr;      // host staging of the table (page-locked)
   size_t pinned_bytes = 0;
@@ -239,6 +435,9 @@ constexpr size_t kAlignB = 256;
 inline size_t alignb(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
 
 bool is_pow2_64(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// leading dimension of a system's running right-hand side (16-byte rows)
+int64_t ldr_for(int64_t k) { return std::max<int64_t>((k + 3) / 4 * 4, 4); }
 
 size_t linv32_offset(int64_t n, int64_t n0) {
   const int64_t m = ceil_div(n, n0);
@@ -264,11 +463,14 @@ void build_list(trsm_batch_s* b, char* ws) {
     s.X = static_cast<T*>(x.X);
     s.ldx = x.ldx;
     s.R = reinterpret_cast<T*>(ws + b->r_off[i]);
-    s.ldr = std::max<int64_t>(x.k, 1);
+    s.ldr = ldr_for(x.k);
     its.push_back(s);
   }
   b->list.clear();
-  record_sweep<T>(b->list, its);
+  if (b->n0 == kPB)
+    record_persist<T>(b->list, its, reinterpret_cast<unsigned*>(ws + b->cnt_off));
+  else
+    record_sweep<T>(b->list, its);
 }
 
 }  // namespace
@@ -303,14 +505,19 @@ trsm_status trsm_batch_create(int32_t count, const trsm_batch_item* items, trsm_
   // table size: record once with a null workspace to measure it
   size_t off = 0;
   b->r_off.resize(count);
+  int64_t tiles = 0;
   for (int32_t i = 0; i < count; ++i) {
     b->r_off[i] = off;
-    off = alignb(off + (size_t)items[i].n * std::max<int64_t>(items[i].k, 1) * es);
+    off = alignb(off + (size_t)items[i].n * ldr_for(items[i].k) * es);
+    if (items[i].n > 0 && items[i].k > 0) tiles += ceil_div(items[i].k, kPB);
   }
+  b->cnt_off = off;
+  off = alignb(off + (size_t)(tiles + 2) * 4);
   if (prec == TRSM_F64) build_list<double>(b, nullptr);
   else build_list<float>(b, nullptr);
   b->table_bytes = alignb(b->list.table_bytes() + 64);
   for (int32_t i = 0; i < count; ++i) b->r_off[i] += b->table_bytes;
+  b->cnt_off += b->table_bytes;
   b->ws_bytes = b->table_bytes + off;
   *out = b;
   return TRSM_OK;
@@ -377,6 +584,20 @@ trsm_status trsm_batch_run(trsm_batch_t b, void* workspace, void* stream, int32_
   b->graph_stream = s;
   hipError_t e5 = hipGraphLaunch(b->exec, s);
   return e5 == hipSuccess ? TRSM_OK : fail(e5);
+}
+
+trsm_status trsm_batch_check(trsm_batch_t b, const void* workspace) {
+  if (!b || !workspace) return TRSM_EINVAL;
+  if (b->n0 != kPB || b->items.empty()) return TRSM_OK;
+  int64_t tiles = 0;
+  for (const auto& x : b->items)
+    if (x.n > 0 && x.k > 0) tiles += ceil_div(x.k, kPB);
+  unsigned err = 0;
+  const char* w = static_cast<const char*>(workspace) + b->cnt_off + (size_t)(tiles + 1) * 4;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&err, w, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return (trsm_status)note_hip_error(e);
+  return err ? TRSM_EHIP : TRSM_OK;
 }
 
 trsm_status trsm_batch_destroy(trsm_batch_t b) {

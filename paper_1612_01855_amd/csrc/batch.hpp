@@ -39,7 +39,32 @@ struct EwEntry {
 
 constexpr int kEwChunk = 4096;  // elements per workgroup in grouped elementwise launches
 
-enum PhaseKind : int { PH_GEMM_F64 = 0, PH_GEMM_F32 = 1, PH_EW = 2 };
+enum PhaseKind : int { PH_GEMM_F64 = 0, PH_GEMM_F32 = 1, PH_EW = 2, PH_PERSIST_F64 = 3,
+                       PH_PERSIST_F32 = 4 };
+
+// Persistent sweep (left-looking Alg. It-Inv-TRSM over many systems in one
+// launch).  A task is (system, step i, column tile c):
+//   R(S_i, c) = B(S_i, c) - L(S_i, 0:i n0) X(0:i n0, c);  X(S_i, c) = Linv_ii R(S_i, c)
+// with n0 = kPB.  Task (i, c) needs tasks (0..i-1, c) of its system: one
+// counter per (system, column tile) holds the number of finished steps.
+constexpr int kPB = 64;          // rows of a step (the block size n0) and columns of a tile
+constexpr int kPersistMaxWG = 1024;
+
+template <typename T>
+struct PersistItem {
+  const T* L; int64_t ldl;
+  const T* Linv;                 // m packed kPB x kPB inverses
+  const T* B; int64_t ldb;
+  T* X; int64_t ldx;
+  T* R; int64_t ldr;             // n x k workspace
+  int n, k, m, nct;              // nct = ceil(k / kPB)
+  int cnt;                       // index of this system's first counter
+  int nb;                        // block size of Linv: kPB, or next_pow2(n) < kPB when m == 1
+};
+
+struct PersistTask {
+  int item, step, ctile, pad;
+};
 
 using GemmP64 = GemmParams<double, double, double, float>;
 using GemmP32 = GemmParams<float, float, float, float>;
@@ -54,6 +79,13 @@ class LaunchList {
   void add_gemm64(const std::vector<GemmP64>& entries);
   void add_gemm32(const std::vector<GemmP32>& entries);
   void add_ew(const std::vector<EwEntry>& entries);
+  // One persistent launch (preceded by clearing its counters): `counters`
+  // (device, ncounters + 2 words: the per-tile counters, the queue head and
+  // an error word that is set if a wait ever gives up) lives in the caller's
+  // workspace.
+  template <typename T>
+  void add_persist(const std::vector<PersistItem<T>>& items, const std::vector<PersistTask>& tasks,
+                   unsigned* counters, int ncounters, bool aligned);
   size_t table_bytes() const { return host_.size(); }
   size_t phases() const { return phases_.size(); }
   // Host copy of the packed table (to be copied to `dev` before run()).
@@ -65,10 +97,13 @@ class LaunchList {
   struct Phase {
     int kind;
     size_t entries_off;  // byte offset of the entry array in the table
-    size_t start_off;    // byte offset of the int prefix array (n + 1 values)
+    size_t start_off;    // byte offset of the int prefix array (n + 1 values); tasks (persistent)
     int count;
     int total;           // workgroups
     bool aligned;
+    unsigned* counters = nullptr;   // persistent: counters, queue head, error word
+    int ncounters = 0;
+    int ntasks = 0;
   };
   template <typename T>
   size_t append(const T* data, size_t n);
@@ -92,6 +127,16 @@ struct SweepItem {
 // of every item goes into the same grouped launch.
 template <typename T>
 void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items);
+
+// Append the persistent sweep for all items (each with n0 == kPB): tasks in
+// step-major order, the systems with the most steps first.  `counters` as in
+// LaunchList::add_persist (one per column tile of every system).
+template <typename T>
+void record_persist(LaunchList& list, const std::vector<SweepItem<T>>& items, unsigned* counters);
+
+// Counter words record_persist needs for these items (tiles + head + error).
+template <typename T>
+int persist_counter_words(const std::vector<SweepItem<T>>& items);
 
 // The block size a plan made with (n, n0) uses: n0 capped at the next power
 // of two >= n.

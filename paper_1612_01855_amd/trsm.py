@@ -70,7 +70,7 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
            "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
            "trsm_plan_timing", "trsm_batch_create", "trsm_batch_workspace_bytes",
-           "trsm_batch_run", "trsm_batch_destroy", "trsm_server_create",
+           "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
            "trsm_server_register_L", "trsm_serve_submit", "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy"]
 
@@ -121,6 +121,8 @@ def _load():
     lib.trsm_batch_workspace_bytes.restype = i32
     lib.trsm_batch_run.argtypes = [vp, vp, vp, ctypes.c_int32]
     lib.trsm_batch_run.restype = i32
+    lib.trsm_batch_check.argtypes = [vp, vp]
+    lib.trsm_batch_check.restype = i32
     lib.trsm_batch_destroy.argtypes = [vp]
     lib.trsm_batch_destroy.restype = i32
     lib.trsm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, i64, ctypes.POINTER(vp)]
@@ -233,6 +235,11 @@ def trsm_batch_workspace_bytes(batch: int) -> int:
 
 def trsm_batch_run(batch: int, workspace: int, stream: int = 0, use_graph: bool = False) -> None:
     _check(_lib.trsm_batch_run(batch, workspace, stream, 1 if use_graph else 0), "trsm_batch_run")
+
+
+def trsm_batch_check(batch: int, workspace: int) -> None:
+    """Blocking: raises if a dependency wait of the persistent sweep gave up."""
+    _check(_lib.trsm_batch_check(batch, workspace), "trsm_batch_check")
 
 
 def trsm_batch_destroy(batch: int) -> None:

@@ -322,11 +322,17 @@ def _run_batch(torch, T, items, prec, n0, use_graph=False, replays=1):
 SHAPES = [(300, 7), (1000, 64), (64, 1), (513, 130), (128, 128), (2000, 33)]
 
 
+ALIGNED_SHAPES = [(256, 64), (1024, 128), (640, 192), (64, 4)]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_batch_matches_oracle_and_is_mix_independent(torch, T, prec):
-    n0 = 128
-    sysd, items = _batch_setup(torch, T, SHAPES, prec, n0, 70)
-    b, ws, _ = _run_batch(torch, T, items, prec, n0)
+@pytest.mark.parametrize("n0,shapes", [(128, SHAPES), (64, SHAPES), (64, ALIGNED_SHAPES)])
+def test_batch_matches_oracle_and_is_mix_independent(torch, T, prec, n0, shapes):
+    # n0 = 64: one persistent launch (left-looking tasks with per-tile
+    # dependency counters); otherwise one grouped launch per sweep phase
+    sysd, items = _batch_setup(torch, T, shapes, prec, n0, 70)
+    b, ws, wsp = _run_batch(torch, T, items, prec, n0)
+    T.trsm_batch_check(b, wsp)
     mixed = [host(d["Xd"]).copy() for d in sysd]
     T.trsm_batch_destroy(b)
     for d, X in zip(sysd, mixed):
@@ -347,8 +353,8 @@ def test_batch_matches_oracle_and_is_mix_independent(torch, T, prec):
         d["s"].close()
 
 
-def test_batch_graph_replays_match_eager(torch, T):
-    n0 = 128
+@pytest.mark.parametrize("n0", [128, 64])
+def test_batch_graph_replays_match_eager(torch, T, n0):
     sysd, items = _batch_setup(torch, T, SHAPES[:4], "f64", n0, 90)
     b, ws, wsp = _run_batch(torch, T, items, "f64", n0)
     eager = [host(d["Xd"]).copy() for d in sysd]
