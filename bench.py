@@ -83,7 +83,7 @@ def serving_bench(args, torch, T, gen, dev):
     import numpy as np
     nf = args.serve_factors
     sizes = gen.serving_factor_sizes(nf, args.seed + 11)
-    n0 = 512
+    n0 = args.serve_n0
     resident = 0
     for n in sizes:
         n0f = min(n0, 1 << (int(n) - 1).bit_length())
@@ -330,6 +330,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-factors", type=int, default=256)
+    ap.add_argument("--serve-n0", type=int, default=512,
+                    help="server block size (64: persistent sweeps)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured saturation rate")

@@ -127,6 +127,7 @@ struct Batch {
   std::vector<std::shared_ptr<Request>> reqs;
   hipEvent_t done = nullptr;
   size_t table_off = SIZE_MAX;
+  size_t cnt_off = SIZE_MAX;  // counters of the persistent sweeps (n0 = kPB)
   std::vector<char> table;   // host copy kept alive until completion
   int stream = 0;
 };
@@ -191,9 +192,11 @@ ReqBufs bufs_of(trsm_server_s* S, const Request& r, int64_t n) {
   return b;
 }
 
-// Record the full refinement pipeline of a group of requests.
+// Record the full refinement pipeline of a group of requests.  With n0 =
+// kPB both binary32 sweeps are persistent launches that share the counter
+// words at `counters` (each launch clears them first; same stream).
 void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request>>& reqs,
-                     LaunchList& list) {
+                     LaunchList& list, unsigned* counters) {
   std::vector<EwEntry> ew_b, ew_in, ew_x0, ew_r, ew_add, ew_out;
   std::vector<SweepItem<float>> sweep;
   std::vector<GemmP64> resid;
@@ -226,16 +229,28 @@ void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request
     ew_add.push_back(EwEntry{b.D, kp, b.X64, kp, n, kp, 1.0, EW_F32_TO_F64_ADD, kp});
     ew_out.push_back(EwEntry{b.X64, kp, r.X, r.ldx, n, k, 1.0, EW_F64_COPY, k});
   }
+  const bool persist = S->n0 == kPB;
   list.clear();
   list.add_ew(ew_b);
   list.add_ew(ew_in);
-  record_sweep<float>(list, sweep);
+  if (persist) record_persist<float>(list, sweep, counters);
+  else record_sweep<float>(list, sweep);
   list.add_ew(ew_x0);
   list.add_gemm64(resid);
   list.add_ew(ew_r);
-  record_sweep<float>(list, sweep);
+  if (persist) record_persist<float>(list, sweep, counters);
+  else record_sweep<float>(list, sweep);
   list.add_ew(ew_add);
   list.add_ew(ew_out);
+}
+
+// Counter words of a group's persistent sweeps (0 when the server sweeps by
+// phases).
+size_t pipeline_counter_bytes(trsm_server_s* S, const std::vector<std::shared_ptr<Request>>& reqs) {
+  if (S->n0 != kPB) return 0;
+  int64_t tiles = 0;
+  for (const auto& rp : reqs) tiles += ceil_div(rp->kp, kPB);
+  return (size_t)(tiles + 2) * 4;
 }
 
 int bucket_of(int64_t m) {
@@ -265,6 +280,8 @@ void complete_batch(trsm_server_s* S, Batch& b, int status) {
     }
   }
   if (b.table_off != SIZE_MAX) S->arena.release(b.table_off);
+  if (b.cnt_off != SIZE_MAX) S->arena.release(b.cnt_off);
+  b.table_off = b.cnt_off = SIZE_MAX;
   if (b.done) (void)hipEventDestroy(b.done);
   b.done = nullptr;
 }
@@ -335,15 +352,22 @@ bool worker_tick(trsm_server_s* S) {
     b.reqs = std::move(groups[gi]);
     b.stream = free_streams[gi];
     LaunchList list;
-    record_pipeline(S, b.reqs, list);
+    int status = TRSM_OK;
+    const size_t cb = pipeline_counter_bytes(S, b.reqs);
+    if (cb) {
+      std::lock_guard<std::mutex> g(S->mu);
+      b.cnt_off = S->arena.alloc(cb);
+      if (b.cnt_off == SIZE_MAX) status = TRSM_ENOMEM;
+    }
+    unsigned* counters = cb && status == TRSM_OK ? (unsigned*)(S->base + b.cnt_off) : nullptr;
+    record_pipeline(S, b.reqs, list, counters);
     const size_t tb = list.table_bytes();
     b.table.assign((const char*)list.host_table(), (const char*)list.host_table() + tb);
-    int status = TRSM_OK;
-    {
+    if (status == TRSM_OK) {
       std::lock_guard<std::mutex> g(S->mu);
       b.table_off = S->arena.alloc(tb);
+      if (b.table_off == SIZE_MAX) status = TRSM_ENOMEM;
     }
-    if (b.table_off == SIZE_MAX) status = TRSM_ENOMEM;
     hipStream_t s = S->streams[b.stream];
     if (status == TRSM_OK) {
       char* dev = S->base + b.table_off;

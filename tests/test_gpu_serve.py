@@ -41,8 +41,9 @@ def wait_all(T, srv, tickets, timeout=60.0):
     return out
 
 
-def test_server_requests_match_oracle_and_mix_independence(torch, T):
-    srv = T.trsm_server_create(2 << 30, 32, 128)
+@pytest.mark.parametrize("n0", [128, 64])   # 64: persistent sweeps
+def test_server_requests_match_oracle_and_mix_independence(torch, T, n0):
+    srv = T.trsm_server_create(2 << 30, 32, n0)
     try:
         ns = [64, 200, 777, 1300]
         Ls, lids = [], []
@@ -92,11 +93,12 @@ def test_server_requests_match_oracle_and_mix_independence(torch, T):
         T.trsm_server_destroy(srv)
 
 
-def test_admission_respects_budget(torch, T):
+@pytest.mark.parametrize("n0", [128, 64])
+def test_admission_respects_budget(torch, T, n0):
     n, k = 1024, 64
     # one factor (~12.6 MB) plus room for about two requests (~2 MB each)
     budget = 20 << 20
-    srv = T.trsm_server_create(budget, 64, 128)
+    srv = T.trsm_server_create(budget, 64, n0)
     try:
         L = gen.easy_lower(n, 7, upper=np.nan)
         Ld = torch.from_numpy(L).cuda()
