@@ -43,16 +43,17 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(workload: str, n0: int):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source with the same block size; else
+    None."""
     path = os.path.join(ROOT, "profiles", f"traffic_gemm_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        if d.get("kernel_sha") != kernel_hash():
+        if d.get("kernel_sha") != kernel_hash() or int(d.get("n0", -1)) != int(n0):
             return None
         return float(d["bytes_per_launch"])
     except Exception:
@@ -280,6 +281,19 @@ def run_suite(args, torch, T, gen, dev):
     del L64
     torch.cuda.empty_cache()
 
+    # measured choice of n0 and tile policy (trsm_autotune) against the cost model
+    for (n, k, prec) in ((8192, 8192, "f64"), (8192, 8192, "f32"), (16384, 128, "f64"),
+                         (16384, 2048, "f64"), (2048, 64, "f64")):
+        r = T.trsm_autotune(n, k, T.PRECISIONS[prec], 3, torch.cuda.current_stream().cuda_stream)
+        emit({"suite": "autotune", "n": n, "k": k, "precision": prec, "n0": int(r.n0),
+              "large_tiles": bool(r.flags & T.FLAG_LARGE_TILES), "ms": round(r.ms, 3),
+              "model_n0": int(r.model_n0), "model_ms": round(r.model_ms, 3),
+              "configurations": int(r.candidates)})
+        log(f"suite autotune {prec} n={n} k={k}: n0={r.n0} flags={r.flags} {r.ms:.2f} ms "
+            f"(model n0={r.model_n0} {r.model_ms:.2f} ms)")
+    T.trsm_autotune_clear()
+    torch.cuda.empty_cache()
+
     # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)
     n = k = 16384
     L64 = gen.chol_lower_on(torch, dev, n, args.seed, ratio=1e-12)
@@ -326,6 +340,8 @@ def main():
     ap.add_argument("--lookahead", action="store_true",
                     help="two-stream lookahead sweep (per-launch timings then overlap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="with --n0 0: use the cost model's n0 instead of trsm_autotune")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true")
@@ -384,6 +400,20 @@ def main():
     Xd = torch.empty_like(Bd)
     torch.cuda.synchronize()
 
+    tune = None
+    if args.n0 == 0 and not args.no_autotune:
+        # n0 and the tile policy measured for this workload (plans made with
+        # n0 = 0 then use the recorded choice)
+        t0 = time.perf_counter()
+        r = T.trsm_autotune(n, k, T.PRECISIONS[args.precision], 3,
+                            torch.cuda.current_stream(dev).cuda_stream)
+        tune = {"n0": int(r.n0), "large_tiles": bool(r.flags & T.FLAG_LARGE_TILES),
+                "ms": round(r.ms, 3), "model_n0": int(r.model_n0),
+                "model_ms": round(r.model_ms, 3), "configurations": int(r.candidates),
+                "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"autotune: n0={r.n0} flags={r.flags} {r.ms:.2f} ms (cost model n0={r.model_n0} "
+            f"{r.model_ms:.2f} ms), {r.candidates} configurations in {tune['seconds']} s")
+        torch.cuda.empty_cache()
     solver = T.Solver.create(n, k, args.precision, args.n0,
                              T.FLAG_LOOKAHEAD if args.lookahead else 0, device=dev)
     info = solver.info
@@ -423,7 +453,7 @@ def main():
     workload = f"trsm_{args.precision}_n{n}_k{k}"
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     peak = PEAK[args.precision]
-    traffic = traffic_from_profiles(workload)
+    traffic = traffic_from_profiles(workload, info.n0)
     roofline = {"bound": "mfma", "kernel": "gemm_kernel (all product launches of a step)",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
@@ -506,7 +536,11 @@ def main():
                    "L": "diag U[1,2], strict lower U[-1,1]/n", "B": "N(0,1)", "seed": args.seed,
                    "step": "trsm_invert_diag + trsm_solve (right-looking sweep"
                            + (", two-stream lookahead)" if args.lookahead else ")"),
-                   "inversion_flops_per_step": info.inv_flops},
+                   "inversion_flops_per_step": info.inv_flops,
+                   "tile_policy": "128x128 only" if info.flags & T.FLAG_LARGE_TILES
+                   else "64x64 + split K for products with few tiles",
+                   "n0_source": "fixed" if args.n0 else ("autotune" if tune else "cost model"),
+                   "autotune": tune},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,

@@ -66,6 +66,10 @@ typedef enum trsm_precision {
 #define TRSM_FLAG_LOOKAHEAD   0x4u  /* F64/F32 sweep: update the next block's rows first and the
                                        rest on a second stream, overlapping the next diagonal
                                        apply (launch timings then overlap) */
+#define TRSM_FLAG_LARGE_TILES 0x8u  /* every product uses 128 x 128 tiles and an unsplit
+                                       reduction (default: products with few tiles use 64 x 64
+                                       tiles and split K); one of the tile policies
+                                       trsm_autotune chooses between */
 
 typedef struct trsm_plan_s* trsm_plan_t;
 
@@ -100,8 +104,9 @@ int trsm_last_hip_error(void);
 
 /*
  * trsm_plan -- choose the blocking for an n x n L and n x k B (host only).
- *  n >= 0, k >= 0.  n0 = 0 picks the block size automatically (a cost model
- *  of one GPU seeded by the Sec. VIII regime rule, rounded to a power of two);
+ *  n >= 0, k >= 0.  n0 = 0 picks the block size automatically (the choice
+ *  trsm_autotune recorded for this size class, else a cost model of one GPU
+ *  seeded by the Sec. VIII regime rule, rounded to a power of two);
  *  otherwise n0 must be a power of two >= 1 (n0 >= n means the full inversion
  *  approach, m = 1).  Returns TRSM_EINVAL for bad arguments, TRSM_ENOMEM if
  *  the plan object cannot be allocated.  *out receives a new plan, owned by
@@ -111,6 +116,43 @@ int trsm_last_hip_error(void);
  */
 trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0,
                       uint32_t flags, trsm_plan_t* out);
+
+/*
+ * trsm_autotune -- the measured counterpart of the n0 rule (Sec. VIII says
+ * the constants are machine dependent and found by experiment).  On the
+ * current device, times trsm_invert_diag + trsm_solve (median of `reps`
+ * runs after one warm run, hipEvents on `stream`) on a synthetic system of
+ * this (n, k, precision) -- diagonal in [1, 2), strict lower entries in
+ * (-1/n, 1/n), right-hand side in (-1/2, 1/2), generated on the device --
+ * for every block size n0 = 32, 64, ..., min(next power of two >= n, 4096)
+ * with at most 256 blocks (n0 >= n / 256) and both tile policies (default, TRSM_FLAG_LARGE_TILES), and records the
+ * fastest in a process-wide table keyed by (precision, ceil(log2 n),
+ * ceil(log2 k)).  trsm_plan with n0 = 0 then uses the recorded n0 (capped
+ * at the next power of two >= n) and adds the recorded tile flag; without a
+ * record it uses the cost model.  Blocking; allocates and frees its own
+ * device buffers (about 8 (n^2 + 4 n k) bytes for binary64).  prec: TRSM_F64
+ * or TRSM_F32.  Returns TRSM_EINVAL for n <= 0, k <= 0, reps <= 0 or a null
+ * `out`, TRSM_ENOMEM if the buffers cannot be allocated.  Thread-safe.
+ */
+typedef struct trsm_tune_result {
+  int64_t n0;          /* fastest block size */
+  uint32_t flags;      /* its tile policy: 0 or TRSM_FLAG_LARGE_TILES */
+  double ms;           /* its median time (invert + solve) */
+  int64_t model_n0;    /* the cost model's choice ... */
+  double model_ms;     /* ... and its median time with the default tile policy */
+  int32_t candidates;  /* configurations timed */
+} trsm_tune_result;
+
+trsm_status trsm_autotune(int64_t n, int64_t k, trsm_precision prec, int32_t reps, void* stream,
+                          trsm_tune_result* out);
+
+/* The recorded choice for (n, k, prec): *n0 = 0 and *flags = 0 if none.
+ * Host only. */
+trsm_status trsm_autotune_lookup(int64_t n, int64_t k, trsm_precision prec, int64_t* n0,
+                                 uint32_t* flags);
+
+/* Forget every recorded choice.  Host only. */
+trsm_status trsm_autotune_clear(void);
 
 /* Fill *info with the plan's choices and buffer sizes (host only). */
 trsm_status trsm_plan_get_info(trsm_plan_t plan, trsm_plan_info* info);

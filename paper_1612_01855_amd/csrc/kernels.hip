@@ -200,6 +200,31 @@ __global__ __launch_bounds__(256) void lowx_kernel(const float* __restrict__ D, 
   }
 }
 
+// Uniform in [0, 1) from a 64-bit counter (splitmix64 finaliser).
+__device__ inline double hash_unit(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename T>
+__global__ void fill_system_kernel(T* __restrict__ L, int64_t n, T* __restrict__ B, int64_t k,
+                                   uint64_t seed) {
+  const int64_t tl = n * n, total = tl + n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double u = hash_unit(seed * 0x100000001B3ull + (uint64_t)e);
+    if (e < tl) {
+      const int64_t i = e / n, j = e - i * n;
+      L[e] = (T)(j == i ? 1.0 + u : (j < i ? (2.0 * u - 1.0) / (double)n : 0.0));
+    } else {
+      B[e - tl] = (T)(u - 0.5);
+    }
+  }
+}
+
 // Recursive baseline leaf: forward substitution, one thread per column.
 template <typename T>
 __global__ __launch_bounds__(64) void subst_leaf_kernel(const T* __restrict__ L, int64_t ldl,
@@ -392,6 +417,17 @@ template hipError_t launch_lowx<f16_t>(const float*, int64_t, int64_t, int64_t, 
                                        unsigned*, float*, int, hipStream_t);
 template hipError_t launch_lowx<fp8_t>(const float*, int64_t, int64_t, int64_t, fp8_t*, int64_t,
                                        unsigned*, float*, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_fill_system(T* L, int64_t n, T* B, int64_t k, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_system_kernel<T><<<grid_for(n * n + n * k, 256, 16384), 256, 0, s>>>(L, n, B, k, seed);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_system<double>(double*, int64_t, double*, int64_t, uint64_t,
+                                               hipStream_t);
+template hipError_t launch_fill_system<float>(float*, int64_t, float*, int64_t, uint64_t,
+                                              hipStream_t);
 
 template <typename T>
 hipError_t launch_subst_leaf(const T* L, int64_t ldl, T* X, int64_t ldx, int64_t nb, int64_t k,

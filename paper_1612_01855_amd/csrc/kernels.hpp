@@ -73,6 +73,13 @@ template <typename TL>
 hipError_t launch_sumsq_lower(const TL* L, int64_t ldl, int64_t n, double* part, double* out,
                               hipStream_t s);
 
+// A synthetic, well-conditioned system for timing runs: L[i][i] in [1, 2),
+// L[i][j] in (-1/n, 1/n) below the diagonal, 0 above; B[i][c] in (-1/2, 1/2)
+// (counter-based hash of (i, j, seed)).  L is n x n, B is n x k, both dense
+// row-major.
+template <typename T>
+hipError_t launch_fill_system(T* L, int64_t n, T* B, int64_t k, uint64_t seed, hipStream_t s);
+
 // Record a HIP error for trsm_last_hip_error() (thread-local); returns
 // TRSM_EHIP's numeric value for convenience.
 int note_hip_error(hipError_t e);

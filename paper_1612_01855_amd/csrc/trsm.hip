@@ -21,6 +21,7 @@
 
 #include "common.hpp"
 #include "gemm.hpp"
+#include "tune.hpp"
 #include "kernels.hpp"
 
 using namespace trsm;
@@ -129,6 +130,15 @@ struct SplitBuf {
   int64_t bytes = 0;
 };
 thread_local SplitBuf g_split;
+
+// Tile policy of the current call (TRSM_FLAG_LARGE_TILES: 128 x 128 only).
+thread_local bool g_large_tiles = false;
+
+struct TilePolicyScope {
+  bool prev;
+  explicit TilePolicyScope(bool large) : prev(g_large_tiles) { g_large_tiles = large; }
+  ~TilePolicyScope() { g_large_tiles = prev; }
+};
 
 struct SplitScope {
   SplitBuf prev;
@@ -256,7 +266,8 @@ struct Gemm {
   static hipError_t run(const P& p0, int batch, hipStream_t s) {
     P p = p0;
     use_split(p);
-    const bool small = (int64_t)gemm_wgs(p.M, p.N, p.K, p.flags, 128, 128) * batch < kSplitTarget;
+    const bool small = !g_large_tiles &&
+                       (int64_t)gemm_wgs(p.M, p.N, p.K, p.flags, 128, 128) * batch < kSplitTarget;
     return timed(gemm_flops(p, batch), s, [&] {
       return small ? launch_gemm<T, T, T, float, 64, 64, 2, 2, false>(p, batch, s)
                    : launch_gemm<T, T, T, float, 128, 128, 2, 2, false>(p, batch, s);
@@ -617,16 +628,27 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   if (prec != TRSM_F64 && prec != TRSM_F32 && !is_mixed(prec)) return TRSM_EINVAL;
   if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
-  if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD)) return TRSM_EINVAL;
+  if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD |
+                TRSM_FLAG_LARGE_TILES))
+    return TRSM_EINVAL;
   if (n * k > ((int64_t)1 << 31) - 1 || n * n > ((int64_t)1 << 31) * 8) return TRSM_EINVAL;
   trsm_plan_s* P = new (std::nothrow) trsm_plan_s();
   if (!P) return TRSM_ENOMEM;
   P->n = n;
   P->k = k;
   P->prec = prec;
-  P->flags = flags;
   P->n0_paper = paper_rule_n0(n, k);
-  if (n0 == 0) n0 = auto_n0(n, k, prec);
+  if (n0 == 0) {
+    int64_t tn0 = 0;
+    uint32_t tfl = 0;
+    if (n > 0 && k > 0 && tune_lookup(n, k, (int)prec, &tn0, &tfl)) {
+      n0 = tn0;
+      flags |= tfl;
+    } else {
+      n0 = auto_n0(n, k, prec);
+    }
+  }
+  P->flags = flags;
   const int64_t cap = next_pow2(n < 1 ? 1 : n);
   if (n0 > cap) n0 = cap;
   P->n0 = n0;
@@ -737,7 +759,10 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
       return TRSM_ENOMEM;
     }
   }
-  SplitScope split_scope(P->d_split, P->d_split ? (int64_t)P->inv_split_bytes : 0);
+  const bool large = P->flags & TRSM_FLAG_LARGE_TILES;
+  TilePolicyScope tile_scope(large);
+  SplitScope split_scope(large ? nullptr : P->d_split,
+                         (P->d_split && !large) ? (int64_t)P->inv_split_bytes : 0);
   TRSM_HIP(hipMemsetAsync(P->d_bad, 0xFF, sizeof(unsigned long long), s));
   if (P->prec == TRSM_F32)
     TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s));
@@ -811,7 +836,9 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   TimerScope timer_scope(&P->timer);
   const char* lb = (const char*)Linv;
   char* ws = (char*)workspace;
-  SplitScope split_scope(ws + P->ws_split, (int64_t)P->ws_split_bytes);
+  const bool large = P->flags & TRSM_FLAG_LARGE_TILES;
+  TilePolicyScope tile_scope(large);
+  SplitScope split_scope(large ? nullptr : ws + P->ws_split, large ? 0 : (int64_t)P->ws_split_bytes);
   if (rec) {
     if (P->prec == TRSM_F64) {
       if (X != B) TRSM_HIP(launch_copy2d<double, double>((const double*)B, ldb, (double*)X, ldx, n, k, 1.0, s));

@@ -29,6 +29,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16, "fp8
 FLAG_NO_REFINE = 0x1
 FLAG_RECURSIVE = 0x2
 FLAG_LOOKAHEAD = 0x4
+FLAG_LARGE_TILES = 0x8
 
 
 class PlanInfo(ctypes.Structure):
@@ -44,6 +45,12 @@ class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("backward_error", ctypes.c_double), ("correction", ctypes.c_double),
                 ("unrefined_error", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("flags", ctypes.c_uint32), ("ms", ctypes.c_double),
+                ("model_n0", ctypes.c_int64), ("model_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -69,7 +76,8 @@ REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_UNKNOWN = range(5)
 EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
            "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
-           "trsm_plan_timing", "trsm_batch_create", "trsm_batch_workspace_bytes",
+           "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
+           "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
            "trsm_server_register_L", "trsm_serve_submit", "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy"]
@@ -114,6 +122,12 @@ def _load():
     lib.trsm_plan_timing.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.trsm_plan_timing.restype = i32
+    lib.trsm_autotune.argtypes = [i64, i64, i32, ctypes.c_int32, vp, ctypes.POINTER(TuneResult)]
+    lib.trsm_autotune.restype = i32
+    lib.trsm_autotune_lookup.argtypes = [i64, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(u32)]
+    lib.trsm_autotune_lookup.restype = i32
+    lib.trsm_autotune_clear.argtypes = []
+    lib.trsm_autotune_clear.restype = i32
     lib.trsm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(BatchItem), i32, i64,
                                       ctypes.POINTER(vp)]
     lib.trsm_batch_create.restype = i32
@@ -235,6 +249,24 @@ def trsm_batch_workspace_bytes(batch: int) -> int:
 
 def trsm_batch_run(batch: int, workspace: int, stream: int = 0, use_graph: bool = False) -> None:
     _check(_lib.trsm_batch_run(batch, workspace, stream, 1 if use_graph else 0), "trsm_batch_run")
+
+
+def trsm_autotune(n: int, k: int, precision: int, reps: int = 3, stream: int = 0) -> TuneResult:
+    r = TuneResult()
+    _check(_lib.trsm_autotune(n, k, precision, reps, stream, ctypes.byref(r)), "trsm_autotune")
+    return r
+
+
+def trsm_autotune_lookup(n: int, k: int, precision: int):
+    """(n0, flags) recorded for this size class, or (0, 0)."""
+    n0, fl = ctypes.c_int64(), ctypes.c_uint32()
+    _check(_lib.trsm_autotune_lookup(n, k, precision, ctypes.byref(n0), ctypes.byref(fl)),
+           "trsm_autotune_lookup")
+    return n0.value, fl.value
+
+
+def trsm_autotune_clear() -> None:
+    _check(_lib.trsm_autotune_clear(), "trsm_autotune_clear")
 
 
 def trsm_batch_check(batch: int, workspace: int) -> None:

@@ -43,7 +43,7 @@ def test_status_strings(T):
 
 
 @pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
-                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x8),
+                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x10),
                                   (8, 8, 2, 0, 2)])
 def test_plan_rejects_bad_arguments(T, args):
     with pytest.raises(T.TrsmError) as e:
@@ -180,3 +180,18 @@ def test_server_argument_validation_without_gpu(T):
     st = ctypes.c_int()
     assert lib.trsm_serve_poll(None, 1, ctypes.byref(st), None) == T.EINVAL
     assert lib.trsm_server_destroy(None) == T.OK
+
+
+def test_autotune_table_without_gpu(T):
+    T.trsm_autotune_clear()
+    assert T.trsm_autotune_lookup(1000, 64, T.F64) == (0, 0)
+    lib = T._lib
+    r = T.TuneResult()
+    for args in [(0, 64, T.F64, 3), (100, 0, T.F64, 3), (100, 64, T.F64, 0),
+                 (100, 64, T.MIXED_BF16, 3)]:
+        assert lib.trsm_autotune(*args, None, ctypes.byref(r)) == T.EINVAL
+    assert lib.trsm_autotune(100, 64, T.F64, 3, None, None) == T.EINVAL
+    # the large-tile policy is a valid plan flag
+    p = T.trsm_plan(300, 20, T.F64, 64, T.FLAG_LARGE_TILES)
+    assert T.trsm_plan_get_info(p).flags == T.FLAG_LARGE_TILES
+    T.trsm_plan_destroy(p)

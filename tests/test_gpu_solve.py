@@ -411,3 +411,28 @@ def test_split_k_products_are_deterministic(torch, T, prec, n, k, n0):
         ref = oracle.trsm(L.astype(np.float32).astype(np.float64),
                           B.astype(np.float32).astype(np.float64))
         assert oracle.rel_fro_err(X0, ref) <= TOL32
+
+
+# ---- autotuner ------------------------------------------------------------------
+
+def test_autotune_records_a_choice_that_plans_use(torch, T):
+    n, k = 1500, 96
+    T.trsm_autotune_clear()
+    model = T.trsm_plan_get_info(T.trsm_plan(n, k, T.F64, 0, 0))
+    r = T.trsm_autotune(n, k, T.F64, 2, torch.cuda.current_stream().cuda_stream)
+    log(f"autotune n={n} k={k}: n0={r.n0} flags={r.flags} {r.ms:.3f} ms "
+        f"(model n0={r.model_n0} {r.model_ms:.3f} ms, {r.candidates} configurations)")
+    assert r.model_n0 == model.n0
+    assert r.n0 in [32, 64, 128, 256, 512, 1024, 2048] and r.flags in (0, T.FLAG_LARGE_TILES)
+    assert 0 < r.ms <= r.model_ms
+    assert T.trsm_autotune_lookup(n, k, T.F64) == (r.n0, r.flags)
+    # a plan asked to choose takes the recorded choice, also for a size of the same class
+    info = T.trsm_plan_get_info(T.trsm_plan(1300, 70, T.F64, 0, 0))
+    assert info.n0 == min(r.n0, 2048) and info.flags == r.flags
+    L, B = gen.easy_system(1300, 70, 5, upper=np.nan)
+    X = gpu_solve(torch, T, L, B)            # n0 = 0: the tuned plan
+    assert oracle.rel_fro_err(X, oracle.trsm(L, B)) <= TOL64
+    X2 = gpu_solve(torch, T, L, B, n0=128, flags=T.FLAG_LARGE_TILES)
+    assert oracle.rel_fro_err(X2, oracle.trsm(L, B)) <= TOL64
+    T.trsm_autotune_clear()
+    assert T.trsm_plan_get_info(T.trsm_plan(n, k, T.F64, 0, 0)).n0 == model.n0
