@@ -66,6 +66,8 @@ constexpr int kBM = 128, kBN = 128;
 // before (the awaited task was taken from the queue earlier by a running
 // workgroup).
 constexpr unsigned kSpinLimit = 1u << 22;
+// Blocks of X folded into a task's running right-hand side per pass.
+constexpr int kPassBlocks = 4;
 
 template <typename T, bool ALIGNED>
 __device__ __forceinline__ void persist_tile(const GemmParams<T, T, T, float>& p) {
@@ -85,11 +87,17 @@ __device__ __forceinline__ GemmParams<T, T, T, float> persist_params() {
 }
 
 // Persistent left-looking sweep over many systems.  Workgroups take tasks
-// from a queue (an atomic head) in step-major order; a task first waits
-// until its column tile's counter shows all earlier steps done (acquire),
-// computes R(S_i, c) and X(S_i, c), and then advances the counter (release).
-// A task only ever waits for a task that was taken from the queue before it,
-// by a workgroup that is running, so every wait ends.
+// (system p, step i, column tile c) from a queue (an atomic head) in
+// step-major order.  A task accumulates R(S_i, c) = B(S_i, c) - sum over the
+// blocks j < i of L(S_i, S_j) X(S_j, c) in passes over fixed groups of
+// kPassBlocks blocks: before a pass it waits until the tile's counter shows
+// the group finished (acquire), and the pass reads and updates R through the
+// epilogue; then X(S_i, c) = Linv_ii R(S_i, c) and the counter advances
+// (release).  Tasks of later steps therefore work through the finished
+// blocks while earlier steps complete, and the fixed groups keep the
+// arithmetic (and so the result bits) independent of timing.  A task only
+// ever waits for tasks taken from the queue before it, by workgroups that
+// are running, so every wait ends.
 template <typename T, bool ALIGNED>
 __global__ __launch_bounds__(256, 2) void persist_sweep_kernel(
     const PersistItem<T>* __restrict__ items, const PersistTask* __restrict__ tasks, int ntasks,
@@ -106,36 +114,40 @@ __global__ __launch_bounds__(256, 2) void persist_sweep_kernel(
     const PersistTask tk = tasks[t];
     const PersistItem<T> it = items[tk.item];
     unsigned* mine = cnt + it.cnt + tk.ctile;
-    if (threadIdx.x == 0 && tk.step > 0) {
-      unsigned spins = 0;
-      while (__hip_atomic_load(mine, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-             (unsigned)tk.step) {
-        __builtin_amdgcn_s_sleep(8);
-        if (++spins > kSpinLimit) {
-          atomicOr(err, 1u);
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    __threadfence();   // acquire for every wave: no stale X(S_j, c) in the caches
     const int nb = it.nb;
     const int r0 = tk.step * nb, sz = min(nb, it.n - r0);
     const int c0 = tk.ctile * kPB, nc = min(kPB, it.k - c0);
-    {
-      // R(S_i, c) = B(S_i, c) - L(S_i, 0:r0) X(0:r0, c)
+    int done = 0;   // blocks of X already folded into R(S_i, c)
+    do {
+      const int avail = min(done + kPassBlocks, tk.step);   // this pass: blocks done..avail-1
+      if (threadIdx.x == 0 && avail > 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(mine, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+               (unsigned)avail) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins > kSpinLimit) {
+            atomicOr(err, 1u);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      __threadfence();   // acquire for every wave: no stale X(S_j, c) in the caches
+      // R(S_i, c) = (first pass ? B : R)(S_i, c) - L(S_i, blocks done..avail) X(..., c)
       auto p = persist_params<T>();
-      p.A = it.L + (int64_t)r0 * it.ldl; p.lda = it.ldl;
-      p.B = it.X + c0; p.ldb = it.ldx;
-      p.Cin = it.B + (int64_t)r0 * it.ldb + c0; p.ldci = it.ldb;
+      p.A = it.L + (int64_t)r0 * it.ldl + (int64_t)done * nb; p.lda = it.ldl;
+      p.B = it.X + (int64_t)done * nb * it.ldx + c0; p.ldb = it.ldx;
+      p.Cin = done == 0 ? it.B + (int64_t)r0 * it.ldb + c0 : it.R + (int64_t)r0 * it.ldr + c0;
+      p.ldci = done == 0 ? it.ldb : it.ldr;
       p.Cout = it.R + (int64_t)r0 * it.ldr + c0; p.ldco = it.ldr;
-      p.M = sz; p.N = nc; p.K = r0;
+      p.M = sz; p.N = nc; p.K = (avail - done) * nb;
       p.alpha = -1.0; p.beta = 1.0;
       p.flags = G_BETA;
       persist_tile<T, ALIGNED>(p);
-    }
-    __threadfence();
-    __syncthreads();
+      done = avail;
+      __threadfence();
+      __syncthreads();
+    } while (done < tk.step);
     {
       // X(S_i, c) = Linv_ii R(S_i, c)
       auto p = persist_params<T>();
