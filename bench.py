@@ -346,8 +346,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-factors", type=int, default=256)
-    ap.add_argument("--serve-n0", type=int, default=512,
-                    help="server block size (64: persistent sweeps)")
+    ap.add_argument("--serve-n0", type=int, default=4096,
+                    help="server block size (>= n: each factor fully inverted at registration; 64: persistent sweeps)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured saturation rate")

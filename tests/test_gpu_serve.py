@@ -41,7 +41,7 @@ def wait_all(T, srv, tickets, timeout=60.0):
     return out
 
 
-@pytest.mark.parametrize("n0", [128, 64])   # 64: persistent sweeps
+@pytest.mark.parametrize("n0", [128, 64, 4096])   # 64: persistent sweeps; 4096: full inverses
 def test_server_requests_match_oracle_and_mix_independence(torch, T, n0):
     srv = T.trsm_server_create(2 << 30, 32, n0)
     try:

@@ -71,6 +71,45 @@ def test_ragged_shapes(torch, T, n, k, n0):
     assert err <= TOL64
 
 
+@pytest.mark.parametrize("n,k", [(0, 5), (6, 0), (0, 0)])
+def test_empty_systems_are_no_ops(torch, T, n, k):
+    # nothing to solve: every call succeeds without touching memory (null
+    # buffers are accepted only because there is nothing to read or write)
+    p = T.trsm_plan(n, k, T.F64, 0, 0)
+    try:
+        info = T.Info()
+        assert T._lib.trsm_invert_diag(p, None, max(n, 1), None, None) in (T.OK, T.EINVAL)
+        assert T._lib.trsm_solve(p, None, max(n, 1), None, None, max(k, 1), None, max(k, 1),
+                                 None, None, info) == T.OK
+    finally:
+        T.trsm_plan_destroy(p)
+    # a batch of empty systems next to a real one
+    L, B = gen.easy_system(100, 3, 7, upper=np.nan)
+    Ld, Bd = dev(torch, L), dev(torch, B)
+    s = T.Solver.create(100, 3, "f64", 32)
+    s.invert(Ld)
+    X = torch.full_like(Bd, float("nan"))
+    items = [T.BatchItem(0, 4, 0, 1, 0, 0, 4, 0, 4),
+             T.BatchItem(100, 3, Ld.data_ptr(), 100, s.linv_ptr, Bd.data_ptr(), 3, X.data_ptr(), 3),
+             T.BatchItem(5, 0, 0, 5, 0, 0, 1, 0, 1)]
+    for n0 in (32, 64):
+        if n0 == 64:
+            s.close()
+            s = T.Solver.create(100, 3, "f64", 64)
+            s.invert(Ld)
+            items[1] = T.BatchItem(100, 3, Ld.data_ptr(), 100, s.linv_ptr, Bd.data_ptr(), 3,
+                                   X.data_ptr(), 3)
+        X.fill_(float("nan"))
+        b = T.trsm_batch_create(items, T.F64, n0)
+        ws = torch.empty(T.trsm_batch_workspace_bytes(b) + 256, dtype=torch.uint8, device="cuda")
+        wsp = (ws.data_ptr() + 255) // 256 * 256
+        T.trsm_batch_run(b, wsp, torch.cuda.current_stream().cuda_stream, False)
+        T.trsm_batch_check(b, wsp)
+        T.trsm_batch_destroy(b)
+        assert oracle.rel_fro_err(host(X), oracle.trsm(L, B)) <= TOL64
+    s.close()
+
+
 @pytest.mark.parametrize("n0", [16, 32, 64, 128, 256, 512, 1024])
 def test_n0_invariance(torch, T, n0):
     # n0 = n is the full inversion approach; small n0 the usual blocked TRSM.
