@@ -43,17 +43,18 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str, n0: int):
+def traffic_from_profiles(workload: str, n0: int, large_tiles: bool):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source with the same block size; else
-    None."""
+    was taken on the current kernel source with the same block size and tile
+    policy; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_gemm_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        if d.get("kernel_sha") != kernel_hash() or int(d.get("n0", -1)) != int(n0):
+        if (d.get("kernel_sha") != kernel_hash() or int(d.get("n0", -1)) != int(n0)
+                or bool(d.get("large_tiles", False)) != bool(large_tiles)):
             return None
         return float(d["bytes_per_launch"])
     except Exception:
@@ -340,6 +341,8 @@ def main():
     ap.add_argument("--lookahead", action="store_true",
                     help="two-stream lookahead sweep (per-launch timings then overlap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--large-tiles", action="store_true",
+                    help="128x128 tiles only (the tile policy trsm_autotune may pick)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="with --n0 0: use the cost model's n0 instead of trsm_autotune")
     ap.add_argument("--no-mixed", action="store_true")
@@ -414,8 +417,8 @@ def main():
         log(f"autotune: n0={r.n0} flags={r.flags} {r.ms:.2f} ms (cost model n0={r.model_n0} "
             f"{r.model_ms:.2f} ms), {r.candidates} configurations in {tune['seconds']} s")
         torch.cuda.empty_cache()
-    solver = T.Solver.create(n, k, args.precision, args.n0,
-                             T.FLAG_LOOKAHEAD if args.lookahead else 0, device=dev)
+    flags = (T.FLAG_LOOKAHEAD if args.lookahead else 0) | (T.FLAG_LARGE_TILES if args.large_tiles else 0)
+    solver = T.Solver.create(n, k, args.precision, args.n0, flags, device=dev)
     info = solver.info
     stream = torch.cuda.current_stream(dev)
     log(f"plan: n0={info.n0} m={info.m} (paper rule n0={info.n0_paper_rule}); "
@@ -453,7 +456,7 @@ def main():
     workload = f"trsm_{args.precision}_n{n}_k{k}"
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     peak = PEAK[args.precision]
-    traffic = traffic_from_profiles(workload, info.n0)
+    traffic = traffic_from_profiles(workload, info.n0, bool(info.flags & T.FLAG_LARGE_TILES))
     roofline = {"bound": "mfma", "kernel": "gemm_kernel (all product launches of a step)",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,

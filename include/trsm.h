@@ -125,9 +125,11 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0,
  * this (n, k, precision) -- diagonal in [1, 2), strict lower entries in
  * (-1/n, 1/n), right-hand side in (-1/2, 1/2), generated on the device --
  * for every block size n0 = 32, 64, ..., min(next power of two >= n, 4096)
- * with at most 256 blocks (n0 >= n / 256) and both tile policies (default, TRSM_FLAG_LARGE_TILES), and records the
- * fastest in a process-wide table keyed by (precision, ceil(log2 n),
- * ceil(log2 k)).  trsm_plan with n0 = 0 then uses the recorded n0 (capped
+ * with at most 256 blocks (n0 >= n / 256) and both tile policies (default,
+ * TRSM_FLAG_LARGE_TILES), and records the fastest -- starting from the cost
+ * model's choice, a configuration replaces the best so far only when it is
+ * at least 1 % faster -- in a process-wide table keyed by (precision,
+ * ceil(log2 n), ceil(log2 k)).  trsm_plan with n0 = 0 then uses the recorded n0 (capped
  * at the next power of two >= n) and adds the recorded tile flag; without a
  * record it uses the cost model.  Blocking; allocates and frees its own
  * device buffers (about 8 (n^2 + 4 n k) bytes for binary64).  prec: TRSM_F64

@@ -18,6 +18,11 @@ namespace trsm {
 
 namespace {
 
+// A candidate replaces the best so far only when it is this much faster, so
+// that timing noise between near-equal configurations does not flip the
+// choice from run to run (the cost model's choice is the first incumbent).
+constexpr double kTuneMargin = 0.01;
+
 struct Choice {
   int64_t n0;
   uint32_t flags;
@@ -153,7 +158,7 @@ trsm_status trsm_autotune(int64_t n, int64_t k, trsm_precision prec, int32_t rep
       st = time_config(n, k, prec, n0, fl, reps, L.p, B.p, X.p, s, &ms);
       if (st != TRSM_OK) return st;
       ++count;
-      if (ms < best_ms) {
+      if (ms < best_ms * (1.0 - kTuneMargin)) {
         best_ms = ms;
         best = Choice{n0, fl};
       }
