@@ -44,7 +44,10 @@ def test_status_strings(T):
 
 @pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
                                   (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x10),
-                                  (8, 8, 2, 0, 2)])
+                                  (8, 8, 2, 0, 2),
+                                  # beyond the addressable sizes: n k > 2^31 - 1, n > 2^30
+                                  (65536, 32769, 0, 0, 0), ((1 << 30) + 1, 1, 0, 0, 0),
+                                  (1, (1 << 30) + 1, 0, 0, 0)])
 def test_plan_rejects_bad_arguments(T, args):
     with pytest.raises(T.TrsmError) as e:
         T.trsm_plan(*args)
@@ -71,7 +74,8 @@ def test_paper_rule_reported(T, n, k, expect):
 
 
 @pytest.mark.parametrize("n,k,n0", [(256, 64, 32), (1000, 7, 0), (1, 1, 0), (0, 5, 0),
-                                    (7, 0, 4), (300, 20, 1024), (8192, 8192, 0)])
+                                    (7, 0, 4), (300, 20, 1024), (8192, 8192, 0),
+                                    (65536, 32767, 0)])   # the largest n k a plan accepts
 def test_plan_layout(T, n, k, n0):
     p = T.trsm_plan(n, k, T.F64, n0, 0)
     try:
