@@ -69,7 +69,7 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_SO)
         i64, dp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
-        for name in ("oracle_trsm_f64", "oracle_trsm_q"):
+        for name in ("oracle_trsm_f64", "oracle_trsm_q", "oracle_trsm_t_f64"):
             f = getattr(lib, name)
             f.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, ci]
             f.restype = ci
@@ -116,6 +116,22 @@ def trsm(L, B, nthreads: int = 0) -> np.ndarray:
                              X.ctypes.data, max(k, 1), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_trsm_f64 rejected the sizes")
+    return X
+
+
+def trsm_t(L, B, nthreads: int = 0) -> np.ndarray:
+    """X = L^{-T} B by backward substitution (the transposed problem L^T X =
+    B).  Reads only the lower triangle of ``L`` (diagonal included)."""
+    lib = _load()
+    L, B = _rows(L), _rows(B)
+    n, k = B.shape
+    if L.shape[0] != n or L.shape[1] < n:
+        raise ValueError("L must be n x n with n = B.shape[0]")
+    X = np.empty((n, k), dtype=np.float64)
+    rc = lib.oracle_trsm_t_f64(n, k, L.ctypes.data, _ld(L), B.ctypes.data, _ld(B),
+                               X.ctypes.data, max(k, 1), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_trsm_t_f64 rejected the sizes")
     return X
 
 

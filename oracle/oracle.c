@@ -93,6 +93,57 @@ int oracle_trsm_f64(int64_t n, int64_t k,
   return 0;
 }
 
+/* Backward substitution with the transpose of L on columns [c0, c1): the
+ * solve L^T X = B, L^T upper triangular with (L^T)[i][j] = l[j][i].  Row i
+ * of X (i descending) starts at b[i][c], then for j = i+1..n-1 in order
+ * subtracts the rounded product l[j][i]*x[j][c], then is divided by l[i][i]. */
+static void subst_t_cols_f64(int64_t n, int64_t c0, int64_t c1,
+                             const double* L, int64_t ldl,
+                             const double* B, int64_t ldb,
+                             double* X, int64_t ldx) {
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double* xi = X + i * ldx;
+    const double* bi = B + i * ldb;
+    if (xi != bi)
+      for (int64_t c = c0; c < c1; ++c) xi[c] = bi[c];
+    for (int64_t j = i + 1; j < n; ++j) {
+      const double lji = L[j * ldl + i];
+      const double* xj = X + j * ldx;
+      for (int64_t c = c0; c < c1; ++c) {
+        double prod = lji * xj[c];
+        xi[c] = xi[c] - prod;
+      }
+    }
+    const double d = L[i * ldl + i];
+    for (int64_t c = c0; c < c1; ++c) xi[c] = xi[c] / d;
+  }
+}
+
+/* X = L^{-T} B by backward substitution: the transposed problem L^T X = B
+ * (the second half of a solve with A = L L^T).  Reads only the lower triangle
+ * of L.  X may be the same buffer as B (with ldx == ldb).  Returns 0, or -1
+ * on bad sizes. */
+int oracle_trsm_t_f64(int64_t n, int64_t k,
+                      const double* L, int64_t ldl,
+                      const double* B, int64_t ldb,
+                      double* X, int64_t ldx, int nthreads) {
+  if (n < 0 || k < 0) return -1;
+  if (n == 0 || k == 0) return 0;
+  if (ldl < n || ldb < k || ldx < k) return -1;
+  const int64_t nchunks = (k + ORACLE_COLS - 1) / ORACLE_COLS;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int64_t c0 = ch * ORACLE_COLS;
+    const int64_t c1 = min64(k, c0 + ORACLE_COLS);
+    subst_t_cols_f64(n, c0, c1, L, ldl, B, ldb, X, ldx);
+  }
+  (void)nthreads;
+  return 0;
+}
+
 /* Residual R = B - L X, summed plainly: r[i][c] = b[i][c] - sum_{j<=i}
  * l[i][j] x[j][c], j ascending, each product rounded then subtracted.
  * This is the postcondition B = L X of Alg. It-Inv-TRSM written as a defect. */
