@@ -66,6 +66,9 @@ typedef enum trsm_precision {
 #define TRSM_FLAG_LOOKAHEAD   0x4u  /* F64/F32 sweep: update the next block's rows first and the
                                        rest on a second stream, overlapping the next diagonal
                                        apply (launch timings then overlap) */
+#define TRSM_FLAG_TRANSPOSE   0x10u /* F64/F32: solve L^T X = B (the transposed problem, upper
+                                       triangular, backward sweep) with the same L; with a
+                                       forward plan this gives A^{-1} B for A = L L^T */
 #define TRSM_FLAG_LARGE_TILES 0x8u  /* every product uses 128 x 128 tiles and an unsplit
                                        reduction (default: products with few tiles use 64 x 64
                                        tiles and split K); one of the tile policies

@@ -13,6 +13,8 @@
 //   past the diagonal are skipped and the diagonal tile is masked, so
 //   whatever is stored above A's diagonal is never used.
 // * G_B_LOWER: B is lower triangular (B[k][j] = 0 for k < j), same treatment.
+// * G_A_UPPER: A is upper triangular and stores zeros below its diagonal;
+//   the chunks left of a tile's diagonal are skipped.
 // * Optional second output C2 (another precision, optionally transposed,
 //   optionally scaled) feeds a following low-precision product.
 // * Batches: z -> offset (z / zdiv) * outer + (z % zdiv) * inner.
@@ -47,6 +49,8 @@ enum GemmFlags : uint32_t {
   G_BETA = 8u,       // read Cin
   G_ROWSCALE = 16u,  // multiply the product by rscale[row * ld_rs]
   G_A_ZERO_UPPER = 32u,  // with G_A_LOWER: A's upper triangle is stored as zeros (no masking)
+  G_A_UPPER = 64u,       // A upper triangular with zeros stored below the diagonal: the
+                         // zero chunks are skipped (no masking)
 };
 
 template <typename TIn, typename TCin, typename TCout, typename TC2>
@@ -95,7 +99,7 @@ __device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, int off) {
 // and row tile ntm-1-t of the same column, so every workgroup gets the same
 // amount of work (and half as many workgroups are launched).
 __host__ __device__ inline bool tri_fold(int M, int K, uint32_t flags, int BM) {
-  return (flags & G_A_LOWER) && M == K && (M + BM - 1) / BM >= 2;
+  return (flags & (G_A_LOWER | G_A_UPPER)) && M == K && (M + BM - 1) / BM >= 2;
 }
 
 // Workgroups one product needs.
@@ -134,6 +138,7 @@ __device__ __forceinline__ int chunk_range(int K, uint32_t flags, int r0, int c0
   int kend = K;
   kbeg = 0;
   if (flags & G_A_LOWER) kend = min(K, r0 + BM);
+  if (flags & G_A_UPPER) kbeg = (min(r0, K) / BK) * BK;
   if (flags & G_B_LOWER) kbeg = (min(c0, K) / BK) * BK;
   return kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 }
@@ -671,7 +676,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
                                           int s, int bid, int nwg) {
   const int ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
   const bool fold = tri_fold(p.M, p.K, p.flags, BM);
-  const bool uniform = fold || !(p.flags & (G_A_LOWER | G_B_LOWER));
+  const bool uniform = fold || !(p.flags & (G_A_LOWER | G_B_LOWER | G_A_UPPER));
   const int rows = fold ? (ntm + 1) / 2 : ntm;
   int slot, tn;
   tile_slot<GROUP_M, XCD_REMAP>(rows, ntn, uniform, bid, nwg, slot, tn);

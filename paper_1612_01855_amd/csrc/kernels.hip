@@ -225,6 +225,35 @@ __global__ void fill_system_kernel(T* __restrict__ L, int64_t n, T* __restrict__
   }
 }
 
+// 64 x 64 tiles transposed through LDS; one workgroup per (matrix, tile).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ in, int64_t ldi,
+                                                        TO* __restrict__ out, int64_t ldo,
+                                                        int64_t rows, int64_t cols, int64_t si,
+                                                        int64_t so, int64_t tiles_per,
+                                                        bool lower_only) {
+  __shared__ TO tile[64][65];
+  const int64_t b = blockIdx.x / tiles_per, t = blockIdx.x % tiles_per;
+  const int64_t ntc = (cols + 63) / 64;
+  const int64_t tr = (t / ntc) * 64, tc = (t % ntc) * 64;
+  const TI* src = in + b * si;
+  TO* dst = out + b * so;
+  const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int64_t r = tr + hi + 4 * j, c = tc + lo;
+    TO v = TO(0);
+    if (r < rows && c < cols && !(lower_only && r < c)) v = (TO)src[r * ldi + c];
+    tile[hi + 4 * j][lo] = v;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int64_t c = tc + hi + 4 * j, r = tr + lo;
+    if (r < rows && c < cols) dst[c * ldo + r] = tile[lo][hi + 4 * j];
+  }
+}
+
 // Recursive baseline leaf: forward substitution, one thread per column.
 template <typename T>
 __global__ __launch_bounds__(64) void subst_leaf_kernel(const T* __restrict__ L, int64_t ldl,
@@ -428,6 +457,23 @@ template hipError_t launch_fill_system<double>(double*, int64_t, double*, int64_
                                                hipStream_t);
 template hipError_t launch_fill_system<float>(float*, int64_t, float*, int64_t, uint64_t,
                                               hipStream_t);
+
+template <typename TI, typename TO>
+hipError_t launch_transpose(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t rows,
+                            int64_t cols, int64_t batch, int64_t si, int64_t so, bool lower_only,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+  const int64_t per = ceil_div(rows, 64) * ceil_div(cols, 64);
+  transpose_kernel<TI, TO><<<(unsigned)(per * batch), 256, 0, s>>>(in, ldi, out, ldo, rows, cols,
+                                                                   si, so, per, lower_only);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose<double, double>(const double*, int64_t, double*, int64_t,
+                                                     int64_t, int64_t, int64_t, int64_t, int64_t,
+                                                     bool, hipStream_t);
+template hipError_t launch_transpose<float, float>(const float*, int64_t, float*, int64_t, int64_t,
+                                                   int64_t, int64_t, int64_t, int64_t, bool,
+                                                   hipStream_t);
 
 template <typename T>
 hipError_t launch_subst_leaf(const T* L, int64_t ldl, T* X, int64_t ldx, int64_t nb, int64_t k,

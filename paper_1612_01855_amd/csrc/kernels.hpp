@@ -80,6 +80,15 @@ hipError_t launch_sumsq_lower(const TL* L, int64_t ldl, int64_t n, double* part,
 template <typename T>
 hipError_t launch_fill_system(T* L, int64_t n, T* B, int64_t k, uint64_t seed, hipStream_t s);
 
+// Transpose of `batch` rows x cols matrices (batch strides si, so elements):
+// out[c*ldo + r] = (TO) in[r*ldi + c]; with lower_only, entries with r < c
+// (above in's diagonal) are written as zeros instead (out is then the upper
+// triangular transpose of in's lower triangle, whose upper part is never read).
+template <typename TI, typename TO>
+hipError_t launch_transpose(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t rows,
+                            int64_t cols, int64_t batch, int64_t si, int64_t so, bool lower_only,
+                            hipStream_t s);
+
 // Record a HIP error for trsm_last_hip_error() (thread-local); returns
 // TRSM_EHIP's numeric value for convenience.
 int note_hip_error(hipError_t e);

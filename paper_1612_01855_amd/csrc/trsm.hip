@@ -179,7 +179,7 @@ template <typename P>
 double gemm_flops(const P& p, int batch) {
   const double M = p.M, N = p.N, K = p.K;
   double f;
-  if ((p.flags & G_A_LOWER) && p.M == p.K) f = M * (M + 1) * N;
+  if ((p.flags & (G_A_LOWER | G_A_UPPER)) && p.M == p.K) f = M * (M + 1) * N;
   else if ((p.flags & G_B_LOWER) && p.K == p.N) f = M * N * (N + 1);
   else f = 2.0 * M * N * K;
   return f * batch;
@@ -192,6 +192,9 @@ struct trsm_plan_s {
   uint32_t flags = 0;
   // Linv buffer layout (byte offsets)
   size_t off_linv64 = 0, off_linv32 = 0, off_llow = 0, off_rscale = 0, off_lnorm = 0, off_lpart = 0;
+  // transposed plans: U = L^T (n x ldu, upper) and the blocks Uinv_ii = Linv_ii^T
+  size_t off_ut = 0, off_uinv = 0;
+  int64_t ldu = 0;
   size_t linv_bytes = 0;
   // workspace layout (byte offsets)
   size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_xsc = 0, ws_part = 0,
@@ -428,6 +431,42 @@ trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, 
   return TRSM_OK;
 }
 
+// The transposed problem L^T X = B: with U = L^T upper triangular the
+// blocked sweep runs backward, right-looking:
+//   X(S_i)   = Uinv_ii B'(S_i)                   (Uinv_ii = Linv_ii^T)
+//   B'(0:i)  = B'(0:i) - U(0:i, S_i) X(S_i)
+// for i = m-1 down to 0; B' lives in the workspace R.
+template <typename T>
+trsm_status sweep_back(trsm_plan_s& P, const T* U, int64_t ldu, const T* Uinv, const T* B,
+                       int64_t ldb, T* X, int64_t ldx, T* R, hipStream_t s) {
+  const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
+  const bool alias = (const void*)X == (const void*)B;
+  const int64_t rl = (m - 1) * n0, szl = n - rl;   // the last (possibly ragged) block
+  const T* srcl = B + rl * ldb;
+  int64_t ld_srcl = ldb;
+  if (alias) {
+    TRSM_HIP(launch_copy2d<T, T>(B + rl * ldb, ldb, R + rl * k, k, szl, k, 1.0, s));
+    srcl = R + rl * k;
+    ld_srcl = k;
+  }
+  for (int64_t i = m - 1; i >= 0; --i) {
+    const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
+    const bool last = i == m - 1;
+    const T* src = last ? srcl : R + r0 * k;
+    const int64_t ld_src = last ? ld_srcl : k;
+    // X(S_i) = Uinv_ii B'(S_i)
+    TRSM_HIP(gemm_simple<T>(Uinv + i * n0 * n0, n0, src, ld_src, nullptr, 0, X + r0 * ldx, ldx,
+                            sz, k, sz, 1.0, 0.0, G_A_UPPER, s));
+    if (i == 0) break;
+    // B'(0:r0) -= U(0:r0, S_i) X(S_i)
+    const T* cin = last ? B : R;
+    const int64_t ldci = last ? ldb : k;
+    TRSM_HIP(gemm_simple<T>(U + r0, ldu, X + r0 * ldx, ldx, cin, ldci, R, k, r0, k, sz, -1.0, 1.0,
+                            0u, s));
+  }
+  return TRSM_OK;
+}
+
 // Recursive baseline (Alg. Rec-TRSM order on one GPU): X1 = solve(L11, B1);
 // B2 -= L21 X1; X2 = solve(L22, B2); substitution leaves, no inversion.
 template <typename T>
@@ -629,7 +668,10 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
   if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD |
-                TRSM_FLAG_LARGE_TILES))
+                TRSM_FLAG_LARGE_TILES | TRSM_FLAG_TRANSPOSE))
+    return TRSM_EINVAL;
+  if ((flags & TRSM_FLAG_TRANSPOSE) &&
+      (is_mixed(prec) || (flags & (TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD))))
     return TRSM_EINVAL;
   if (n * k > ((int64_t)1 << 31) - 1 || n * n > ((int64_t)1 << 31) * 8) return TRSM_EINVAL;
   trsm_plan_s* P = new (std::nothrow) trsm_plan_s();
@@ -672,6 +714,14 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     off = align_up(off + 8);
     P->off_lpart = off;
     off = align_up(off + 2 * kNormBlocks * 8 + 16);
+  }
+  if (flags & TRSM_FLAG_TRANSPOSE) {
+    const size_t es = elem_size(prec);
+    P->ldu = (n + 3) / 4 * 4;
+    P->off_ut = off;
+    off = align_up(off + (size_t)n * P->ldu * es);
+    P->off_uinv = off;
+    off = align_up(off + (size_t)m * n0 * n0 * es);
   }
   P->linv_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : off;
   // workspace
@@ -775,6 +825,22 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
   }
   if (P->prec != TRSM_F64)
     TRSM_HIP((launch_convert<double, float>(L64, (float*)(base + P->off_linv32), m * n0 * n0, s)));
+  if (P->flags & TRSM_FLAG_TRANSPOSE) {
+    // U = L^T (zeros below the diagonal) and Uinv_ii = Linv_ii^T
+    if (P->prec == TRSM_F32) {
+      TRSM_HIP((launch_transpose<float, float>((const float*)L, ldl, (float*)(base + P->off_ut),
+                                               P->ldu, n, n, 1, 0, 0, true, s)));
+      TRSM_HIP((launch_transpose<float, float>((const float*)(base + P->off_linv32), n0,
+                                               (float*)(base + P->off_uinv), n0, n0, n0, m,
+                                               n0 * n0, n0 * n0, false, s)));
+    } else {
+      TRSM_HIP((launch_transpose<double, double>((const double*)L, ldl,
+                                                 (double*)(base + P->off_ut), P->ldu, n, n, 1, 0,
+                                                 0, true, s)));
+      TRSM_HIP((launch_transpose<double, double>(L64, n0, (double*)(base + P->off_uinv), n0, n0,
+                                                 n0, m, n0 * n0, n0 * n0, false, s)));
+    }
+  }
   if (is_mixed(P->prec)) {
     float* rs = (float*)(base + P->off_rscale);
     if (P->prec == TRSM_MIXED_BF16)
@@ -846,6 +912,15 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
     }
     if (X != B) TRSM_HIP(launch_copy2d<float, float>((const float*)B, ldb, (float*)X, ldx, n, k, 1.0, s));
     return rec_solve<float>(n, k, (const float*)L, ldl, (float*)X, ldx, 64, s);
+  }
+  if (P->flags & TRSM_FLAG_TRANSPOSE) {
+    if (P->prec == TRSM_F64)
+      return sweep_back<double>(*P, (const double*)(lb + P->off_ut), P->ldu,
+                                (const double*)(lb + P->off_uinv), (const double*)B, ldb,
+                                (double*)X, ldx, (double*)(ws + P->ws_r), s);
+    return sweep_back<float>(*P, (const float*)(lb + P->off_ut), P->ldu,
+                             (const float*)(lb + P->off_uinv), (const float*)B, ldb, (float*)X,
+                             ldx, (float*)(ws + P->ws_r), s);
   }
   switch (P->prec) {
     case TRSM_F64:

@@ -30,6 +30,7 @@ FLAG_NO_REFINE = 0x1
 FLAG_RECURSIVE = 0x2
 FLAG_LOOKAHEAD = 0x4
 FLAG_LARGE_TILES = 0x8
+FLAG_TRANSPOSE = 0x10
 
 
 class PlanInfo(ctypes.Structure):

@@ -43,7 +43,7 @@ def test_status_strings(T):
 
 
 @pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
-                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x10),
+                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x20),
                                   (8, 8, 2, 0, 2),
                                   # beyond the addressable sizes: n k > 2^31 - 1, n > 2^30
                                   (65536, 32769, 0, 0, 0), ((1 << 30) + 1, 1, 0, 0, 0),
@@ -199,3 +199,21 @@ def test_autotune_table_without_gpu(T):
     p = T.trsm_plan(300, 20, T.F64, 64, T.FLAG_LARGE_TILES)
     assert T.trsm_plan_get_info(p).flags == T.FLAG_LARGE_TILES
     T.trsm_plan_destroy(p)
+
+
+def test_transposed_plans(T):
+    p0 = T.trsm_plan(300, 20, T.F64, 64, 0)
+    p1 = T.trsm_plan(300, 20, T.F64, 64, T.FLAG_TRANSPOSE)
+    try:
+        a, b = T.trsm_plan_get_info(p0), T.trsm_plan_get_info(p1)
+        # L^T (300 x 300 with rows of 300) and the transposed blocks are kept too
+        assert b.linv_bytes >= a.linv_bytes + 300 * 300 * 8 + 5 * 64 * 64 * 8
+        assert b.workspace_bytes == a.workspace_bytes
+    finally:
+        T.trsm_plan_destroy(p0)
+        T.trsm_plan_destroy(p1)
+    for prec, flags in [(T.MIXED_BF16, T.FLAG_TRANSPOSE),
+                        (T.F64, T.FLAG_TRANSPOSE | T.FLAG_RECURSIVE),
+                        (T.F64, T.FLAG_TRANSPOSE | T.FLAG_LOOKAHEAD)]:
+        with pytest.raises(T.TrsmError):
+            T.trsm_plan(300, 20, prec, 64, flags)

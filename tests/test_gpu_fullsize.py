@@ -199,3 +199,16 @@ def test_mixed_hard_n16384_k16384(torch, T, prec):
     else:
         # not converged is reported, never hidden behind a passing stop test
         assert info.backward_error > 4 * 2.0 ** -53
+
+
+def test_transposed_f64_n16384_k16384(torch, T):
+    n = k = 16384
+    L, B = gen.easy_system(n, k, 7, upper=np.nan)
+    cols = sample_cols(k, 107)
+    Xs, X = gpu_solve_cols(torch, T, torch.from_numpy(L).cuda(), torch.from_numpy(B).cuda(),
+                           "f64", n0=2048, flags=T.FLAG_TRANSPOSE, cols=cols)
+    del X
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle.trsm_t(L, np.ascontiguousarray(B[:, cols])))
+    log(f"full size transposed f64: sampled rel err {err:.2e}")
+    assert err <= TOL64

@@ -475,3 +475,46 @@ def test_autotune_records_a_choice_that_plans_use(torch, T):
     assert oracle.rel_fro_err(X2, oracle.trsm(L, B)) <= TOL64
     T.trsm_autotune_clear()
     assert T.trsm_plan_get_info(T.trsm_plan(n, k, T.F64, 0, 0)).n0 == model.n0
+
+
+# ---- the transposed problem L^T X = B ----------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,k,n0", [(1, 1, 0), (7, 3, 4), (33, 5, 16), (1000, 64, 128),
+                                    (513, 77, 256), (700, 96, 1024), (130, 300, 1)])
+def test_transposed_solve_matches_oracle(torch, T, prec, n, k, n0):
+    L, B = gen.easy_system(n, k, 300 + n, upper=np.nan)
+    X = gpu_solve(torch, T, L, B, precision=prec, n0=n0, flags=T.FLAG_TRANSPOSE)
+    if prec == "f32":
+        ref = oracle.trsm_t(L.astype(np.float32).astype(np.float64),
+                            B.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    else:
+        ref, tol = oracle.trsm_t(L, B), TOL64
+    err = oracle.rel_fro_err(X, ref)
+    log(f"transposed {prec} n={n} k={k} n0={n0}: rel err {err:.2e}")
+    assert err <= tol
+
+
+def test_transposed_in_place_and_cholesky_solve(torch, T):
+    # A = L L^T: X = L^{-T} (L^{-1} B), a forward and a transposed plan on the
+    # same L; the second solve runs in place
+    n, k = 900, 40
+    L = gen.chol_lower(n, 8, upper=np.nan)
+    B = gen.rhs(n, k, 8)
+    Ld, Bd = dev(torch, L), dev(torch, B)
+    sf = T.Solver.create(n, k, "f64", 128)
+    st = T.Solver.create(n, k, "f64", 128, T.FLAG_TRANSPOSE)
+    sf.invert(Ld)
+    st.invert(Ld)
+    Y = sf.solve(Ld, Bd)
+    st.solve(Ld, Y, Y)                       # in place: X overwrites Y
+    torch.cuda.synchronize()
+    ref = oracle.trsm_t(L, oracle.trsm(L, B))
+    A = np.tril(np.nan_to_num(L)) @ np.tril(np.nan_to_num(L)).T
+    err = oracle.rel_fro_err(host(Y), ref)
+    log(f"cholesky solve n={n}: rel err vs oracle {err:.2e}, "
+        f"residual {np.linalg.norm(A @ host(Y) - B) / np.linalg.norm(B):.1e}")
+    assert err <= TOL64
+    sf.close()
+    st.close()
