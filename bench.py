@@ -76,11 +76,12 @@ def cpu_baseline(L, B, seconds_hint: float = 15.0):
                       f"(columns are independent), binary64 forward substitution"}
 
 
-def serving_bench(args, torch, T, gen, dev):
+def serving_bench(args, torch, T, gen, dev, chol=False):
     """Continuous-batching serving: resident factors with cached inverted
     blocks, Poisson arrivals of binary64 solves (binary32 sweeps + one binary64
     refinement step).  Reports saturation throughput and p50/p99 latency at a
-    fixed arrival rate."""
+    fixed arrival rate.  chol: the factors are registered as Cholesky factors
+    and every request solves A X = B with A = L L^T."""
     import math
     import numpy as np
     nf = args.serve_factors
@@ -88,9 +89,10 @@ def serving_bench(args, torch, T, gen, dev):
     n0 = args.serve_n0
     resident = 0
     for n in sizes:
-        n0f = min(n0, 1 << (int(n) - 1).bit_length())
+        n0f = min(n0, 512 if chol else n0, 1 << (int(n) - 1).bit_length())
         m = -(-int(n) // n0f)
-        resident += 12 * int(n) * (int(n) + 4) + 12 * m * n0f * n0f + 4096
+        per = 12 * int(n) * (int(n) + 4) + 12 * m * n0f * n0f + 4096
+        resident += per + (12 * int(n) * (int(n) + 4) + 4 * m * n0f * n0f if chol else 0)
     budget = resident + (6 << 30)
     srv = T.trsm_server_create(budget, 512, n0)
     try:
@@ -104,7 +106,8 @@ def serving_bench(args, torch, T, gen, dev):
             L = torch.tril(L, -1)
             L.diagonal().copy_(torch.rand(n, generator=g, device=dev, dtype=torch.float64) + 1.0)
             torch.cuda.synchronize()
-            lids.append(T.trsm_server_register_L(srv, L.data_ptr(), n, n))
+            reg = T.trsm_server_register_chol if chol else T.trsm_server_register_L
+            lids.append(reg(srv, L.data_ptr(), n, n))
             del L
         log(f"serving: registered {nf} factors (n in [{int(sizes.min())}, {int(sizes.max())}]) "
             f"in {time.perf_counter() - t0:.1f} s; resident {resident / 2**30:.2f} GiB")
@@ -138,7 +141,7 @@ def serving_bench(args, torch, T, gen, dev):
                     if st == T.REQ_DONE:
                         n, k = outstanding.pop(t)
                         lat.append(l_us)
-                        flops += float(n) * n * k
+                        flops += (2.0 if chol else 1.0) * float(n) * n * k
                     elif st == T.REQ_ERROR:
                         raise RuntimeError(f"serving request failed: {T.status_string(status)}")
                 if i < len(bufs) and timed_arrivals:
@@ -186,7 +189,8 @@ def serving_bench(args, torch, T, gen, dev):
         out = {"factors": nf, "n_range": [int(sizes.min()), int(sizes.max())],
                "k_range": [1, 512], "saturation_rps": round(sat_rps, 1),
                "hbm_budget_gib": round(budget / 2**30, 2), "n0_max": n0,
-               "precision": "binary64 in/out; binary32 sweeps + one binary64 refinement step"}
+               "precision": "binary64 in/out; binary32 sweeps + one binary64 refinement step",
+               "problem": "A X = B, A = L L^T (flops 2 n^2 k)" if chol else "L X = B"}
         out.update(headline)
         out["rate_sweep"] = sweep
         return out
@@ -310,6 +314,12 @@ def run_suite(args, torch, T, gen, dev):
         log(f"suite autotune {prec} n={n} k={k}: n0={r.n0} flags={r.flags} {r.ms:.2f} ms "
             f"(model n0={r.model_n0} {r.model_ms:.2f} ms)")
     T.trsm_autotune_clear()
+    torch.cuda.empty_cache()
+
+    # serving with Cholesky factors: every request solves A X = B, A = L L^T
+    res = serving_bench(args, torch, T, gen, dev, chol=True)
+    emit({"suite": "serving_cholesky", **{k_: res[k_] for k_ in res if k_ != "rate_sweep"},
+          "rate_sweep": res.get("rate_sweep")})
     torch.cuda.empty_cache()
 
     # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)

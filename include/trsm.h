@@ -295,6 +295,13 @@ trsm_status trsm_batch_destroy(trsm_batch_t batch);
  *  inverts its diagonal blocks (Alg. Diagonal-Inverter) once; blocking.
  *  TRSM_ENOMEM if it does not fit the budget, TRSM_ESINGULAR for a zero or
  *  non-finite diagonal.
+ * trsm_server_register_chol(srv, L, n, ldl, &l_id): the same for a Cholesky
+ *  factor: requests on it solve A X = B for A = L L^T (forward sweep with L,
+ *  backward sweep with L^T, binary64 residual B - L (L^T X), one refinement
+ *  step).  The server also keeps L^T and its inverted blocks (about twice the
+ *  memory of a triangular factor); n^2 k flops count twice for these.  Their
+ *  block size is min(n0, 512): larger inverted blocks leave the single
+ *  refinement step too little accuracy margin on A's squared conditioning.
  * trsm_serve_submit(srv, l_id, B, k, ldb, X, ldx, &ticket): never blocks.
  *  B (read) and X (written) are caller-owned binary64 device matrices (n x k,
  *  row-major) that must stay valid until the ticket is DONE or ERROR.  The
@@ -335,6 +342,8 @@ trsm_status trsm_server_create(size_t hbm_budget, int32_t max_slots, int64_t n0,
                                trsm_server_t* out);
 trsm_status trsm_server_register_L(trsm_server_t srv, const double* L, int64_t n, int64_t ldl,
                                    int32_t* l_id);
+trsm_status trsm_server_register_chol(trsm_server_t srv, const double* L, int64_t n, int64_t ldl,
+                                      int32_t* l_id);
 trsm_status trsm_serve_submit(trsm_server_t srv, int32_t l_id, const double* B, int64_t k,
                               int64_t ldb, double* X, int64_t ldx, uint64_t* ticket);
 trsm_status trsm_serve_poll(trsm_server_t srv, uint64_t ticket, trsm_req_state* state,

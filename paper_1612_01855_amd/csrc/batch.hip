@@ -361,6 +361,53 @@ template void record_sweep<double>(LaunchList&, const std::vector<SweepItem<doub
 template void record_sweep<float>(LaunchList&, const std::vector<SweepItem<float>>&);
 
 template <typename T>
+void record_sweep_back(LaunchList& list, const std::vector<SweepItem<T>>& items) {
+  int64_t max_m = 0;
+  for (const auto& it : items) max_m = std::max(max_m, ceil_div(it.n, it.n0));
+  for (int64_t j = 0; j < max_m; ++j) {
+    std::vector<GemmParams<T, T, T, float>> diag, upd;
+    for (const auto& it : items) {
+      const int64_t n0 = it.n0;
+      const int64_t m = ceil_div(it.n, n0);
+      if (j >= m || it.k == 0) continue;
+      const int64_t i = m - 1 - j;
+      const int64_t r0 = i * n0, sz = std::min(n0, it.n - r0);
+      // X(S_i) = Uinv_ii * B'(S_i)
+      auto p = gemm_params<T, T, T, float>();
+      p.A = it.Linv + i * n0 * n0; p.lda = n0;
+      p.B = (j == 0) ? it.B + r0 * it.ldb : it.R + r0 * it.ldr;
+      p.ldb = (j == 0) ? it.ldb : it.ldr;
+      p.Cout = it.X + r0 * it.ldx; p.ldco = it.ldx;
+      p.M = (int)sz; p.N = (int)it.k; p.K = (int)sz;
+      p.flags = G_A_UPPER;
+      diag.push_back(p);
+      if (i > 0) {
+        // B'(0:r0) = B'(0:r0) - U(0:r0, S_i) X(S_i)
+        auto q = gemm_params<T, T, T, float>();
+        q.A = it.L + r0; q.lda = it.ldl;
+        q.B = it.X + r0 * it.ldx; q.ldb = it.ldx;
+        q.Cin = (j == 0) ? it.B : it.R;
+        q.ldci = (j == 0) ? it.ldb : it.ldr;
+        q.Cout = it.R; q.ldco = it.ldr;
+        q.M = (int)r0; q.N = (int)it.k; q.K = (int)sz;
+        q.alpha = -1.0; q.beta = 1.0;
+        q.flags = G_BETA;
+        upd.push_back(q);
+      }
+    }
+    if constexpr (std::is_same<T, double>::value) {
+      list.add_gemm64(diag);
+      list.add_gemm64(upd);
+    } else {
+      list.add_gemm32(diag);
+      list.add_gemm32(upd);
+    }
+  }
+}
+template void record_sweep_back<double>(LaunchList&, const std::vector<SweepItem<double>>&);
+template void record_sweep_back<float>(LaunchList&, const std::vector<SweepItem<float>>&);
+
+template <typename T>
 int persist_counter_words(const std::vector<SweepItem<T>>& items) {
   int64_t c = 0;
   for (const auto& it : items)

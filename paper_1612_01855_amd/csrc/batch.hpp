@@ -128,6 +128,13 @@ struct SweepItem {
 template <typename T>
 void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items);
 
+// Append the backward sweep of the transposed problem for all items: here
+// L is U = L^T (upper triangular, zeros below the diagonal) and Linv holds
+// the blocks Uinv_ii = Linv_ii^T; phase j of every item is its step
+// i = m - 1 - j: X(S_i) = Uinv_ii B'(S_i), B'(0:i n0) -= U(0:i n0, S_i) X(S_i).
+template <typename T>
+void record_sweep_back(LaunchList& list, const std::vector<SweepItem<T>>& items);
+
 // Append the persistent sweep for all items (each with n0 == kPB): tasks in
 // step-major order, the systems with the most steps first.  `counters` as in
 // LaunchList::add_persist (one per column tile of every system).

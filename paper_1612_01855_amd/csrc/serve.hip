@@ -37,6 +37,7 @@ using namespace trsm;
 namespace {
 
 constexpr size_t kAl = 256;
+constexpr int64_t kCholMaxN0 = 512;
 inline size_t al(size_t v) { return (v + kAl - 1) / kAl * kAl; }
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -107,6 +108,12 @@ struct Factor {
   float* L32 = nullptr;   int64_t ld32 = 0;
   double* Linv64 = nullptr;
   float* Linv32 = nullptr;
+  // Cholesky factors (requests solve A X = B, A = L L^T): U = L^T and the
+  // transposed inverse blocks
+  bool chol = false;
+  double* U64 = nullptr;
+  float* U32 = nullptr;
+  float* Uinv32 = nullptr;
 };
 
 struct Request {
@@ -164,46 +171,61 @@ struct trsm_server_s {
 
 namespace {
 
-size_t factor_bytes(int64_t n, int64_t n0) {
+size_t factor_bytes(int64_t n, int64_t n0, bool chol) {
   const int64_t m = ceil_div(n, n0);
-  return al((size_t)n * round_up(n, 2) * 8) + al((size_t)n * round_up(n, 4) * 4) +
-         al((size_t)m * n0 * n0 * 8) + al((size_t)m * n0 * n0 * 4);
+  size_t b = al((size_t)n * round_up(n, 2) * 8) + al((size_t)n * round_up(n, 4) * 4) +
+             al((size_t)m * n0 * n0 * 8) + al((size_t)m * n0 * n0 * 4);
+  if (chol)
+    b += al((size_t)n * round_up(n, 2) * 8) + al((size_t)n * round_up(n, 4) * 4) +
+         al((size_t)m * n0 * n0 * 4);
+  return b;
 }
 
 // Internal buffers of a request are kp = round_up(k, 4) columns wide (zero
 // padded) so that every product takes the 16-byte vector path.
-size_t request_bytes(int64_t n, int64_t kp) {
-  // B, X, R (binary64), running RHS and correction (binary32)
-  return 3 * al((size_t)n * kp * 8) + 2 * al((size_t)n * kp * 4);
+size_t request_bytes(int64_t n, int64_t kp, bool chol) {
+  // B, X, R (binary64), running RHS and correction (binary32); for A = L L^T
+  // also the backward sweep's output (binary32) and L^T X (binary64)
+  size_t b = 3 * al((size_t)n * kp * 8) + 2 * al((size_t)n * kp * 4);
+  if (chol) b += al((size_t)n * kp * 4) + al((size_t)n * kp * 8);
+  return b;
 }
 
 struct ReqBufs {
   double* B64; double* X64; double* R64; float* Rl; float* D;
+  float* E; double* T64;   // Cholesky requests only
 };
 
-ReqBufs bufs_of(trsm_server_s* S, const Request& r, int64_t n) {
+ReqBufs bufs_of(trsm_server_s* S, const Request& r, int64_t n, bool chol) {
   char* p = S->base + r.ws_off;
-  ReqBufs b;
+  ReqBufs b{};
   b.B64 = (double*)p; p += al((size_t)n * r.kp * 8);
   b.X64 = (double*)p; p += al((size_t)n * r.kp * 8);
   b.R64 = (double*)p; p += al((size_t)n * r.kp * 8);
   b.Rl = (float*)p;   p += al((size_t)n * r.kp * 4);
-  b.D = (float*)p;
+  b.D = (float*)p;    p += al((size_t)n * r.kp * 4);
+  if (chol) {
+    b.E = (float*)p;    p += al((size_t)n * r.kp * 4);
+    b.T64 = (double*)p;
+  }
   return b;
 }
 
 // Record the full refinement pipeline of a group of requests.  With n0 =
 // kPB both binary32 sweeps are persistent launches that share the counter
 // words at `counters` (each launch clears them first; same stream).
+// Requests on Cholesky factors (A = L L^T) add a backward sweep with U = L^T
+// after each forward sweep, and their residual B - L (U X) takes one more
+// binary64 product.
 void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request>>& reqs,
                      LaunchList& list, unsigned* counters) {
   std::vector<EwEntry> ew_b, ew_in, ew_x0, ew_r, ew_add, ew_out;
-  std::vector<SweepItem<float>> sweep;
-  std::vector<GemmP64> resid;
+  std::vector<SweepItem<float>> sweep, back;
+  std::vector<GemmP64> resid_u, resid;
   for (const auto& rp : reqs) {
     const Request& r = *rp;
     const Factor& f = S->factors[r.l_id];
-    const ReqBufs b = bufs_of(S, r, f.n);
+    const ReqBufs b = bufs_of(S, r, f.n, f.chol);
     const int n = (int)f.n, k = (int)r.k, kp = (int)r.kp;
     ew_b.push_back(EwEntry{r.B, r.ldb, b.B64, kp, n, kp, 1.0, EW_F64_COPY, k});
     ew_in.push_back(EwEntry{r.B, r.ldb, b.Rl, kp, n, kp, 1.0, EW_F64_TO_F32, k});
@@ -215,10 +237,31 @@ void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request
     it.X = b.D; it.ldx = kp;
     it.R = b.Rl; it.ldr = kp;
     sweep.push_back(it);
-    ew_x0.push_back(EwEntry{b.D, kp, b.X64, kp, n, kp, 1.0, EW_F32_TO_F64_SET, kp});
+    float* sol = b.D;                  // the binary32 solution of one pass
+    const double* prod = b.X64;        // what L multiplies in the residual
+    if (f.chol) {
+      SweepItem<float> u{};
+      u.n = f.n; u.k = kp; u.n0 = f.n0;
+      u.L = f.U32; u.ldl = f.ld32;     // upper triangular
+      u.Linv = f.Uinv32;
+      u.B = b.D; u.ldb = kp;
+      u.X = b.E; u.ldx = kp;
+      u.R = b.Rl; u.ldr = kp;          // free again after the forward pass
+      back.push_back(u);
+      sol = b.E;
+      auto q = gemm_params<double, double, double, float>();
+      q.A = f.U64; q.lda = f.ld64;     // T = L^T X
+      q.B = b.X64; q.ldb = kp;
+      q.Cout = b.T64; q.ldco = kp;
+      q.M = n; q.N = kp; q.K = n;
+      q.flags = G_A_UPPER;
+      resid_u.push_back(q);
+      prod = b.T64;
+    }
+    ew_x0.push_back(EwEntry{sol, kp, b.X64, kp, n, kp, 1.0, EW_F32_TO_F64_SET, kp});
     auto p = gemm_params<double, double, double, float>();
     p.A = f.L64; p.lda = f.ld64;
-    p.B = b.X64; p.ldb = kp;
+    p.B = prod; p.ldb = kp;
     p.Cin = b.B64; p.ldci = kp;
     p.Cout = b.R64; p.ldco = kp;
     p.M = n; p.N = kp; p.K = n;
@@ -226,20 +269,24 @@ void record_pipeline(trsm_server_s* S, const std::vector<std::shared_ptr<Request
     p.flags = G_A_LOWER | G_BETA;
     resid.push_back(p);
     ew_r.push_back(EwEntry{b.R64, kp, b.Rl, kp, n, kp, 1.0, EW_F64_TO_F32, kp});
-    ew_add.push_back(EwEntry{b.D, kp, b.X64, kp, n, kp, 1.0, EW_F32_TO_F64_ADD, kp});
+    ew_add.push_back(EwEntry{sol, kp, b.X64, kp, n, kp, 1.0, EW_F32_TO_F64_ADD, kp});
     ew_out.push_back(EwEntry{b.X64, kp, r.X, r.ldx, n, k, 1.0, EW_F64_COPY, k});
   }
   const bool persist = S->n0 == kPB;
+  auto sweeps = [&] {
+    if (persist) record_persist<float>(list, sweep, counters);
+    else record_sweep<float>(list, sweep);
+    if (!back.empty()) record_sweep_back<float>(list, back);
+  };
   list.clear();
   list.add_ew(ew_b);
   list.add_ew(ew_in);
-  if (persist) record_persist<float>(list, sweep, counters);
-  else record_sweep<float>(list, sweep);
+  sweeps();
   list.add_ew(ew_x0);
+  if (!resid_u.empty()) list.add_gemm64(resid_u);
   list.add_gemm64(resid);
   list.add_ew(ew_r);
-  if (persist) record_persist<float>(list, sweep, counters);
-  else record_sweep<float>(list, sweep);
+  sweeps();
   list.add_ew(ew_add);
   list.add_ew(ew_out);
 }
@@ -272,8 +319,9 @@ void complete_batch(trsm_server_s* S, Batch& b, int status) {
     if (status == TRSM_OK) {
       S->completed += 1;
       S->lat_us.push_back(r.t_done - r.t_submit);
-      const double n = (double)S->factors[r.l_id].n;
-      S->flops_done += n * n * (double)r.k;
+      const Factor& f = S->factors[r.l_id];
+      const double n = (double)f.n;
+      S->flops_done += (f.chol ? 2.0 : 1.0) * n * n * (double)r.k;
       S->t_last = t;
     } else {
       S->failed += 1;
@@ -314,7 +362,7 @@ bool worker_tick(trsm_server_s* S) {
     while (!S->pending.empty() && S->slots_used < S->max_slots) {
       auto rp = S->pending.front();
       const Factor& f = S->factors[rp->l_id];
-      const size_t need = request_bytes(f.n, rp->kp);
+      const size_t need = request_bytes(f.n, rp->kp, f.chol);
       const size_t off = S->arena.alloc(need);
       if (off == SIZE_MAX) {
         // cannot fit now; if it can never fit (nothing else holds memory), fail it
@@ -440,14 +488,23 @@ trsm_status trsm_server_create(size_t hbm_budget, int32_t max_slots, int64_t n0,
   return TRSM_OK;
 }
 
-trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, int64_t ldl,
-                                   int32_t* l_id) {
+}  // extern "C"
+
+namespace {
+
+trsm_status register_factor(trsm_server_t S, const double* L, int64_t n, int64_t ldl, bool chol,
+                            int32_t* l_id) {
   if (!S || !L || !l_id || n <= 0 || ldl < n || n > (1 << 20)) return TRSM_EINVAL;
   Factor f;
   f.n = n;
-  f.n0 = effective_n0(n, S->n0);
+  // A = L L^T solves square L's conditioning and pass the binary32 error of
+  // two sweeps to the single refinement step; fully inverted blocks of more
+  // than kCholMaxN0 rows left too little margin to 1e-12 (measured), so
+  // Cholesky factors use at most that block size.
+  f.n0 = effective_n0(n, chol ? std::min<int64_t>(S->n0, kCholMaxN0) : S->n0);
   f.m = ceil_div(n, f.n0);
-  f.bytes = factor_bytes(n, f.n0);
+  f.chol = chol;
+  f.bytes = factor_bytes(n, f.n0, chol);
   {
     std::lock_guard<std::mutex> g(S->mu);
     f.off = S->arena.alloc(f.bytes);
@@ -459,10 +516,15 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
   f.ld32 = round_up(n, 4);
   f.L32 = (float*)p; p += al((size_t)n * f.ld32 * 4);
   f.Linv64 = (double*)p; p += al((size_t)f.m * f.n0 * f.n0 * 8);
-  f.Linv32 = (float*)p;
+  f.Linv32 = (float*)p; p += al((size_t)f.m * f.n0 * f.n0 * 4);
+  if (chol) {
+    f.U64 = (double*)p; p += al((size_t)n * f.ld64 * 8);
+    f.U32 = (float*)p; p += al((size_t)n * f.ld32 * 4);
+    f.Uinv32 = (float*)p;
+  }
   hipStream_t s = S->streams[0];
   trsm_plan_t plan = nullptr;
-  trsm_status st = trsm_plan(n, 1, TRSM_F64, S->n0, 0, &plan);
+  trsm_status st = trsm_plan(n, 1, TRSM_F64, f.n0, 0, &plan);   // the factor's own block size
   hipError_t e = hipSuccess;
   if (st == TRSM_OK) {
     e = launch_copy2d<double, double>(L, ldl, f.L64, f.ld64, n, n, 1.0, s);
@@ -470,6 +532,15 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
     if (e == hipSuccess) st = trsm_invert_diag(plan, f.L64, f.ld64, f.Linv64, s);
     if (st == TRSM_OK && e == hipSuccess)
       e = launch_convert<double, float>(f.Linv64, f.Linv32, f.m * f.n0 * f.n0, s);
+    if (chol && st == TRSM_OK && e == hipSuccess) {
+      // U = L^T (zeros below the diagonal) and Uinv_ii = Linv_ii^T
+      e = launch_transpose<double, double>(f.L64, f.ld64, f.U64, f.ld64, n, n, 1, 0, 0, true, s);
+      if (e == hipSuccess)
+        e = launch_transpose<float, float>(f.L32, f.ld32, f.U32, f.ld32, n, n, 1, 0, 0, true, s);
+      if (e == hipSuccess)
+        e = launch_transpose<float, float>(f.Linv32, f.n0, f.Uinv32, f.n0, f.n0, f.n0, f.m,
+                                           f.n0 * f.n0, f.n0 * f.n0, false, s);
+    }
     if (st == TRSM_OK && e == hipSuccess) e = hipStreamSynchronize(s);
     if (st == TRSM_OK && e == hipSuccess) {
       trsm_status le;
@@ -488,6 +559,20 @@ trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, 
   S->factors.push_back(f);
   *l_id = (int32_t)S->factors.size() - 1;
   return TRSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+trsm_status trsm_server_register_L(trsm_server_t S, const double* L, int64_t n, int64_t ldl,
+                                   int32_t* l_id) {
+  return register_factor(S, L, n, ldl, false, l_id);
+}
+
+trsm_status trsm_server_register_chol(trsm_server_t S, const double* L, int64_t n, int64_t ldl,
+                                      int32_t* l_id) {
+  return register_factor(S, L, n, ldl, true, l_id);
 }
 
 trsm_status trsm_serve_submit(trsm_server_t S, int32_t l_id, const double* B, int64_t k,

@@ -80,7 +80,7 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
            "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
-           "trsm_server_register_L", "trsm_serve_submit", "trsm_serve_poll",
+           "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy"]
 
 
@@ -144,6 +144,8 @@ def _load():
     lib.trsm_server_create.restype = i32
     lib.trsm_server_register_L.argtypes = [vp, vp, i64, i64, ctypes.POINTER(ctypes.c_int32)]
     lib.trsm_server_register_L.restype = i32
+    lib.trsm_server_register_chol.argtypes = [vp, vp, i64, i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.trsm_server_register_chol.restype = i32
     lib.trsm_serve_submit.argtypes = [vp, ctypes.c_int32, vp, i64, i64, vp, i64,
                                       ctypes.POINTER(ctypes.c_uint64)]
     lib.trsm_serve_submit.restype = i32
@@ -290,6 +292,14 @@ def trsm_server_register_L(srv: int, L: int, n: int, ldl: int) -> int:
     lid = ctypes.c_int32()
     _check(_lib.trsm_server_register_L(srv, L, n, ldl, ctypes.byref(lid)),
            "trsm_server_register_L")
+    return lid.value
+
+
+def trsm_server_register_chol(server: int, L: int, n: int, ldl: int) -> int:
+    """Register L as the Cholesky factor of A = L L^T: requests solve A X = B."""
+    lid = ctypes.c_int32()
+    _check(_lib.trsm_server_register_chol(server, L, n, ldl, ctypes.byref(lid)),
+           "trsm_server_register_chol")
     return lid.value
 
 

@@ -130,3 +130,56 @@ def test_admission_respects_budget(torch, T, n0):
         assert st == T.REQ_ERROR and status == T.ENOMEM
     finally:
         T.trsm_server_destroy(srv)
+
+
+@pytest.mark.parametrize("n0", [128, 4096])
+def test_cholesky_factors_mixed_with_triangular_ones(torch, T, n0):
+    # factors registered as Cholesky factors answer A X = B with A = L L^T;
+    # triangular and Cholesky requests share batches
+    srv = T.trsm_server_create(2 << 30, 32, n0)
+    try:
+        spec = [(150, True), (600, False), (1100, True), (333, True), (3000, True)]
+        Ls, lids = [], []
+        for i, (n, chol) in enumerate(spec):
+            L = gen.chol_lower(n, 200 + i, upper=np.nan) if chol else \
+                gen.easy_lower(n, 200 + i, upper=np.nan)
+            Ld = torch.from_numpy(L).cuda()
+            reg = T.trsm_server_register_chol if chol else T.trsm_server_register_L
+            lids.append(reg(srv, Ld.data_ptr(), n, n))
+            Ls.append(L)
+            del Ld
+        torch.cuda.synchronize()
+        g = gen.rng(9)
+        reqs = []
+        for r in range(14):
+            f = int(g.integers(0, len(spec)))
+            k = int(gen.log_uniform_int(g, 1, 200))
+            B = gen.rhs(spec[f][0], k, 700 + r)
+            Bd = torch.from_numpy(B).cuda()
+            reqs.append(dict(f=f, k=k, B=B, Bd=Bd, Xd=torch.full_like(Bd, float("nan"))))
+        torch.cuda.synchronize()
+        tickets = [T.trsm_serve_submit(srv, lids[q["f"]], q["Bd"].data_ptr(), q["k"], q["k"],
+                                       q["Xd"].data_ptr(), q["k"]) for q in reqs]
+        res = wait_all(T, srv, tickets)
+        mix = []
+        for q, t in zip(reqs, tickets):
+            st, status, lat = res[t]
+            assert st == T.REQ_DONE and status == T.OK
+            L = Ls[q["f"]]
+            ref = oracle.trsm_t(L, oracle.trsm(L, q["B"])) if spec[q["f"]][1] else \
+                oracle.trsm(L, q["B"])
+            X = q["Xd"].cpu().numpy()
+            err = oracle.rel_fro_err(X, ref)
+            print(f"{'cholesky' if spec[q['f']][1] else 'triangular'} n={spec[q['f']][0]} "
+                  f"k={q['k']}: rel err {err:.2e}", flush=True)
+            assert err <= 1e-12
+            mix.append(X.copy())
+        for q, X in zip(reqs[:5], mix[:5]):
+            q["Xd"].fill_(float("nan"))
+            torch.cuda.synchronize()
+            t = T.trsm_serve_submit(srv, lids[q["f"]], q["Bd"].data_ptr(), q["k"], q["k"],
+                                    q["Xd"].data_ptr(), q["k"])
+            assert wait_all(T, srv, [t])[t][0] == T.REQ_DONE
+            assert np.array_equal(q["Xd"].cpu().numpy(), X)
+    finally:
+        T.trsm_server_destroy(srv)
