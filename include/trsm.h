@@ -5,7 +5,8 @@
  * Parallel Algorithms for Solving Triangular Systems of Linear Equations"):
  * given a lower-triangular n x n matrix L and a dense n x k matrix B, find the
  * dense n x k matrix X with  L X = B.  Left side, lower triangle, no
- * transpose, non-unit diagonal, no scaling factor.
+ * transpose, non-unit diagonal, no scaling factor (plans made with
+ * TRSM_FLAG_TRANSPOSE solve L^T X = B with the same L instead).
  *
  * Method (Sec. VI, Alg. Diagonal-Inverter and Alg. It-Inv-TRSM): the n0 x n0
  * diagonal blocks L(S_i, S_i), S_i = i*n0 : (i+1)*n0, are inverted by
@@ -45,7 +46,7 @@ typedef enum trsm_status {
   TRSM_ESINGULAR = 2,      /* a diagonal entry of L is zero or not finite */
   TRSM_ENOMEM = 3,         /* a device allocation failed or a budget is too small */
   TRSM_EHIP = 4,           /* the HIP runtime reported an error (see trsm_last_hip_error) */
-  TRSM_ENOTCONVERGED = 5,  /* refinement hit its iteration cap; X holds the best iterate */
+  TRSM_ENOTCONVERGED = 5,  /* refinement hit its iteration cap; X holds the last iterate */
   TRSM_EBUSY = 6           /* serving: no free slot and queuing was refused */
 } trsm_status;
 
@@ -203,6 +204,9 @@ trsm_status trsm_plan_last_error(trsm_plan_t plan, trsm_status* status, int64_t*
  *  With TRSM_FLAG_RECURSIVE the plan solves by the recursive baseline
  *  (Alg. Rec-TRSM order: X1 = solve(L11, B1); B2 -= L21 X1; X2 = solve(L22,
  *  B2), substitution at the leaves, no inversion) and Linv may be NULL.
+ *  With TRSM_FLAG_TRANSPOSE the plan solves L^T X = B: trsm_invert_diag
+ *  also stored U = L^T and the inverses of U's diagonal blocks in Linv
+ *  (linv_bytes covers them), and the sweep runs from the last block up.
  */
 trsm_status trsm_solve(trsm_plan_t plan, const void* L, int64_t ldl, const void* Linv,
                        const void* B, int64_t ldb, void* X, int64_t ldx, void* workspace,
@@ -288,8 +292,10 @@ trsm_status trsm_batch_destroy(trsm_batch_t batch);
  *  ONE device block of hbm_budget bytes on the current device and never more;
  *  factors and in-flight requests are carved from it ("admission by HBM
  *  budget").  At most max_slots requests are in flight.  n0 (power of two)
- *  is the diagonal block size used for every factor.  A worker thread and
- *  four streams (default priority) are created.  Thread-safe afterwards.
+ *  is the diagonal block size used for every factor, capped at the next
+ *  power of two >= the factor's n (so n0 >= n inverts the whole factor:
+ *  each request is then one product per sweep).  A worker thread and four
+ *  streams (default priority) are created.  Thread-safe afterwards.
  * trsm_server_register_L(srv, L, n, ldl, &l_id): copies the binary64 lower
  *  triangle of L (device pointer) into the server, makes a binary32 copy and
  *  inverts its diagonal blocks (Alg. Diagonal-Inverter) once; blocking.
@@ -305,7 +311,8 @@ trsm_status trsm_batch_destroy(trsm_batch_t batch);
  * trsm_serve_submit(srv, l_id, B, k, ldb, X, ldx, &ticket): never blocks.
  *  B (read) and X (written) are caller-owned binary64 device matrices (n x k,
  *  row-major) that must stay valid until the ticket is DONE or ERROR.  The
- *  request waits until its workspace (32 n k bytes, k rounded up to 4) fits the budget
+ *  request waits until its workspace (32 n k bytes with k rounded up to 4;
+ *  44 n k on a Cholesky factor) fits the budget
  *  and a slot is free, then joins the next batch, which runs on one of the
  *  server's streams while earlier batches may still be running.  Each
  *  request is solved with binary32 sweeps and one refinement step with a
@@ -316,7 +323,8 @@ trsm_status trsm_batch_destroy(trsm_batch_t batch);
  *  completion observed by the worker, in microseconds.  Returns the
  *  request's error status for ERROR.
  * trsm_server_stats / trsm_server_reset_stats: counters, p50/p99/mean
- *  latency of completed requests, n^2 k flops completed, memory in use.
+ *  latency of completed requests, n^2 k flops completed (2 n^2 k for a
+ *  Cholesky factor), memory in use.
  * trsm_server_destroy: waits for queued and in-flight work, frees everything.
  */
 typedef enum trsm_req_state {
@@ -330,7 +338,8 @@ typedef enum trsm_req_state {
 typedef struct trsm_serve_stats {
   uint64_t submitted, completed, failed, batches;
   double p50_us, p99_us, mean_us;
-  double flops_done;       /* sum of n^2 k over completed requests */
+  double flops_done;       /* sum of n^2 k over completed requests (2 n^2 k on
+                              Cholesky factors) */
   double wall_s;           /* first submit to last completion */
   size_t hbm_budget, hbm_in_use, resident_bytes;
   int32_t queue_depth, in_flight, max_in_flight, factors;

@@ -497,10 +497,10 @@ trsm_status register_factor(trsm_server_t S, const double* L, int64_t n, int64_t
   if (!S || !L || !l_id || n <= 0 || ldl < n || n > (1 << 20)) return TRSM_EINVAL;
   Factor f;
   f.n = n;
-  // A = L L^T solves square L's conditioning and pass the binary32 error of
-  // two sweeps to the single refinement step; fully inverted blocks of more
-  // than kCholMaxN0 rows left too little margin to 1e-12 (measured), so
-  // Cholesky factors use at most that block size.
+  // A = L L^T has the square of L's condition number, and the single
+  // refinement step must remove the binary32 error of two sweeps; fully
+  // inverted blocks of more than kCholMaxN0 rows left too little margin to
+  // 1e-12 (measured), so Cholesky factors use at most that block size.
   f.n0 = effective_n0(n, chol ? std::min<int64_t>(S->n0, kCholMaxN0) : S->n0);
   f.m = ceil_div(n, f.n0);
   f.chol = chol;
