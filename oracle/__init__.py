@@ -21,6 +21,11 @@ What it computes (all in IEEE binary64 unless stated):
 * ``residual(L, X, B)`` -- B - L X summed plainly (the postcondition B = L X
   written as a defect).
 * ``trsm_q(L, B)`` -- the same substitution in binary128, rounded once.
+* ``trsm_t(L, B)`` -- X = L^{-T} B by backward substitution (the transposed
+  problem, the second half of a solve with A = L L^T).
+* ``chol(A)`` -- the Cholesky factor A = L L^T of a symmetric positive
+  definite A by its column-by-column definition (the factorization whose
+  panel step is a triangular solve, named in the abstract and Sec. I).
 * ``oracle.exact`` -- exact rational arithmetic (Gauss-Jordan on Q) for
   brute-force pins at tiny n.
 
@@ -47,6 +52,7 @@ _lock = threading.Lock()
 
 CFLAGS = ["-O2", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
           "-fno-fast-math", "-ffp-contract=off", "-std=gnu11"]
+LIBS = ["-lquadmath", "-lm"]
 
 
 def build(force: bool = True) -> str:
@@ -54,7 +60,7 @@ def build(force: bool = True) -> str:
     os.makedirs(_BUILD_DIR, exist_ok=True)
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lquadmath"]
+        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, *LIBS]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _SO)
     return _SO
@@ -79,6 +85,8 @@ def _load():
         lib.oracle_fro_lower.restype = ctypes.c_double
         lib.oracle_fro_dense.argtypes = [i64, i64, dp, i64]
         lib.oracle_fro_dense.restype = ctypes.c_double
+        lib.oracle_chol_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
+        lib.oracle_chol_f64.restype = ci
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ci
         _lib = lib
@@ -192,6 +200,25 @@ def diag_block_inverses(L, n0: int) -> list:
         e = min(s + n0, n)
         out.append(inv_lower(L[s:e, s:e]))
     return out
+
+
+def chol(A, nthreads: int = 0):
+    """Cholesky factor of a symmetric positive definite A (lower triangle
+    read): returns (L, fail) with L lower triangular, zeros above the
+    diagonal, A = L L^T, and fail = -1, or the first column whose pivot is not
+    positive (L's columns from there on are then unspecified)."""
+    lib = _load()
+    A = _rows(A)
+    n = A.shape[0]
+    if A.shape[1] < n:
+        raise ValueError("A must be n x n")
+    L = np.empty((n, n), dtype=np.float64)
+    fail = ctypes.c_int64(-1)
+    rc = lib.oracle_chol_f64(n, A.ctypes.data, _ld(A), L.ctypes.data, max(n, 1),
+                             int(nthreads), ctypes.byref(fail))
+    if rc != 0:
+        raise ValueError("oracle_chol_f64 rejected the sizes")
+    return L, int(fail.value)
 
 
 def rel_fro_err(X, Xref) -> float:

@@ -33,6 +33,7 @@
 #include <stddef.h>
 #include <string.h>
 #include <stdlib.h>
+#include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -238,6 +239,72 @@ double oracle_fro_dense(int64_t n, int64_t k, const double* A, int64_t lda) {
   __float128 r = (__float128)__builtin_sqrt(s64);
   for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);
   return (double)r;
+}
+
+/* Cholesky factor of a symmetric positive definite A: the lower-triangular L
+ * with positive diagonal and A = L L^T.  The factorization whose panel step
+ * is a triangular solve with many right-hand sides (the abstract and Sec. I
+ * name Cholesky and LU as the factorizations TRSM serves).  The definition
+ * written out column by column, j ascending:
+ *
+ *     l[j][j] = sqrt( a[j][j] - sum_{p<j} l[j][p]^2 )
+ *     l[i][j] = ( a[i][j] - sum_{p<j} l[i][p] * l[j][p] ) / l[j][j],   i > j,
+ *
+ * each sum taken with p ascending, every product rounded before it is
+ * subtracted, a correctly rounded square root and a true division.  Only the
+ * lower triangle of A (diagonal included) is read; L is written to the lower
+ * triangle of Lout with zeros above the diagonal.  Lout may be A itself
+ * (ldl == lda).  Threads split the rows of each column: every element is
+ * computed by the same operations whatever the thread count.
+ *
+ * Returns 0, or -1 on bad sizes.  *fail receives -1, or the first column j
+ * whose pivot a[j][j] - sum l[j][p]^2 is not positive (or is NaN); the
+ * factorization stops there and columns >= j of Lout are unspecified. */
+int oracle_chol_f64(int64_t n, const double* A, int64_t lda,
+                    double* Lout, int64_t ldl, int nthreads, int64_t* fail) {
+  if (fail) *fail = -1;
+  if (n < 0) return -1;
+  if (n == 0) return 0;
+  if (lda < n || ldl < n) return -1;
+  /* copy the lower triangle first so that Lout == A works */
+  for (int64_t i = 0; i < n; ++i) {
+    double* li = Lout + i * ldl;
+    const double* ai = A + i * lda;
+    if (li != ai)
+      for (int64_t j = 0; j <= i; ++j) li[j] = ai[j];
+    for (int64_t j = i + 1; j < n; ++j) li[j] = 0.0;
+  }
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#endif
+  for (int64_t j = 0; j < n; ++j) {
+    double* lj = Lout + j * ldl;
+    double piv = lj[j];
+    for (int64_t p = 0; p < j; ++p) {
+      double prod = lj[p] * lj[p];
+      piv = piv - prod;
+    }
+    if (!(piv > 0.0)) {
+      if (fail) *fail = j;
+      return 0;
+    }
+    const double d = sqrt(piv);
+    lj[j] = d;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (n - j > 256)
+#endif
+    for (int64_t i = j + 1; i < n; ++i) {
+      double* li = Lout + i * ldl;
+      double v = li[j];
+      for (int64_t p = 0; p < j; ++p) {
+        double prod = li[p] * lj[p];
+        v = v - prod;
+      }
+      li[j] = v / d;
+    }
+  }
+  (void)nthreads;
+  return 0;
 }
 
 /* Number of threads the OpenMP runtime would use by default. */

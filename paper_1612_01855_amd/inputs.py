@@ -15,6 +15,8 @@ its problem statement, an n x n lower-triangular L and a dense n x k B):
 * ``hard_lower``  -- L = chol(G G^T / m + eps I) with G of size n x n/2 (so
   G G^T has rank n/2) and eps = 1e-12 * ||G G^T / m||_2: cond_2(A) ~ 1e12,
   hence cond_2(L) ~ 1e6.
+* ``spd`` / ``spd_on`` -- the symmetric positive definite A = G G^T / m + I
+  (or + eps I) behind the Cholesky factors, the input of the factorization.
 * ``rhs``         -- B ~ N(0,1).
 * closed-form matrices used as pins (identity, diagonal, bidiagonal,
   all-ones lower triangle, random integer unit-lower).
@@ -128,6 +130,58 @@ def chol_lower_on(torch, device, n: int, seed: int, m: Optional[int] = None,
     L = torch.linalg.cholesky(A)
     del A
     return L.tril_().contiguous()
+
+
+def spd(n: int, seed: int, m: Optional[int] = None) -> np.ndarray:
+    """A = G G^T / m + I, G ~ N(0,1) n x m (m = 2n by default): the symmetric
+    positive definite matrix whose Cholesky factor chol_lower returns (same
+    seed, same G).  Full symmetric float64, row-major."""
+    m = 2 * n if m is None else m
+    g = rng(seed)
+    G = g.standard_normal(size=(n, m))
+    A = G @ G.T
+    A *= 1.0 / m
+    A[np.arange(n), np.arange(n)] += 1.0
+    return np.ascontiguousarray(A)
+
+
+def spd_on(torch, device, n: int, seed: int, m: Optional[int] = None,
+           ratio: Optional[float] = None):
+    """The symmetric positive definite matrices behind chol_lower_on, formed
+    by torch on `device` from the same seeded G: A = G G^T / m + I
+    (ratio=None, m = 2n by default) or A = G G^T / m + ratio * lambda_max I
+    (m = n/2 by default; cond_2(A) ~ 1/ratio).  A float64 tensor, full
+    symmetric (the product's two triangles are computed separately, so they
+    may differ in the last bit)."""
+    if m is None:
+        m = 2 * n if ratio is None else max(n // 2, 1)
+    g = rng(seed)
+    G = torch.from_numpy(g.standard_normal(size=(n, m))).to(device)
+    A = G @ G.t().contiguous()
+    del G
+    A *= 1.0 / m
+    if ratio is None:
+        A.diagonal().add_(1.0)
+    else:
+        v = torch.from_numpy(g.standard_normal(size=n)).to(device)
+        lam = 0.0
+        for _ in range(50):
+            w = A @ v
+            lam = float(torch.linalg.norm(w).item())
+            v = w / lam
+        A.diagonal().add_(ratio * lam)
+    return A
+
+
+def int_lower_positive(n: int, seed: int, lo: int = -2, hi: int = 2,
+                       dmax: int = 3) -> np.ndarray:
+    """Integer lower-triangular matrix: diagonal in {1..dmax}, strict lower
+    entries in {lo..hi}, zeros above.  A = L L^T then has integer entries and
+    L is its Cholesky factor exactly."""
+    g = rng(seed)
+    L = np.tril(g.integers(lo, hi + 1, size=(n, n)), -1).astype(np.float64)
+    L[np.arange(n), np.arange(n)] = g.integers(1, dmax + 1, size=n)
+    return L
 
 
 # ---- closed-form matrices (pins) -------------------------------------------

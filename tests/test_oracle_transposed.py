@@ -119,7 +119,7 @@ MUTANTS = {
 def _compile(src, tmp_path):
     c, so = tmp_path / "mut_t.c", tmp_path / "mut_t.so"
     c.write_text(src)
-    subprocess.run(["gcc", *oracle.CFLAGS, str(c), "-o", str(so), "-lquadmath"], check=True)
+    subprocess.run(["gcc", *oracle.CFLAGS, str(c), "-o", str(so), *oracle.LIBS], check=True)
     lib = ctypes.CDLL(str(so))
     i64, dp = ctypes.c_int64, ctypes.c_void_p
     lib.oracle_trsm_t_f64.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, ctypes.c_int]
