@@ -362,6 +362,45 @@ trsm_status trsm_server_reset_stats(trsm_server_t srv);
 trsm_status trsm_server_destroy(trsm_server_t srv);
 
 /*
+ * Blocked Cholesky factorization A = L L^T (binary64) with the triangular
+ * solve of Alg. It-Inv-TRSM as its panel step (the abstract and Sec. I name
+ * Cholesky as a factorization built on TRSM).  Right-looking with block size
+ * nb: for each diagonal block S_j, factor A(S_j, S_j) = L_jj L_jj^T (recursive
+ * halving down to 64 x 64 leaves factored in LDS) and form Linv_jj = L_jj^{-1}
+ * along the way by Alg. RecTriInv's combine; the panel solve L(T_j, S_j) =
+ * A(T_j, S_j) Linv_jj^T is one matrix-core product (the whole block inverted:
+ * the one-large-dimension regime of Sec. VIII, nb columns against n - (j+1) nb
+ * rows); then A(T_j, T_j) -= L(T_j, S_j) L(T_j, S_j)^T on the lower triangle.
+ *
+ * trsm_chol_sizes(n, nb, &nb_used, &linv_bytes, &workspace_bytes): host only.
+ *  nb = 0 picks min(256, the next power of two >= max(n, 64)); otherwise nb
+ *  must be a power of two in [64, 4096].  TRSM_EINVAL for n < 0, n > 2^20 or
+ *  a bad nb.  Any output pointer may be NULL.
+ * trsm_chol_factor(n, A, lda, nb, Linv, workspace, stream): A is a device
+ *  binary64 row-major n x n matrix (lda >= n) of which only the lower
+ *  triangle (diagonal included) is read; on return its lower triangle holds
+ *  L and the strict upper triangle is untouched.  Linv (device, linv_bytes,
+ *  16-byte aligned) receives the inverted diagonal blocks: block j at Linv +
+ *  j*nb*nb, nb x nb row-major, zeros above the diagonal, the ragged last
+ *  block padded with the identity -- the layout trsm_invert_diag fills for a
+ *  TRSM_F64 plan with n0 = nb_used (n > 32), so such a plan can solve with
+ *  L and these blocks directly (their values agree with trsm_invert_diag's
+ *  up to rounding).  workspace: workspace_bytes of device memory, 256-byte
+ *  aligned; its first 8 bytes hold the status word trsm_chol_check reads.
+ *  Asynchronous on `stream`; no memory is allocated.  Returns TRSM_EINVAL for
+ *  bad sizes, null or misaligned pointers.
+ * trsm_chol_check(workspace, &status, &index): blocking (synchronises the
+ *  device).  After trsm_chol_factor: TRSM_OK and -1, or TRSM_ESINGULAR and
+ *  the first row whose pivot was not positive (A is not positive definite,
+ *  or NaN); L and Linv are then unspecified from that row's block on.
+ */
+trsm_status trsm_chol_sizes(int64_t n, int64_t nb, int64_t* nb_used, size_t* linv_bytes,
+                            size_t* workspace_bytes);
+trsm_status trsm_chol_factor(int64_t n, double* A, int64_t lda, int64_t nb, double* Linv,
+                             void* workspace, void* stream);
+trsm_status trsm_chol_check(const void* workspace, trsm_status* status, int64_t* index);
+
+/*
  * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes
  * every matrix-core product launched by trsm_invert_diag and trsm_solve with
  * this plan record a pair of hipEvents around itself on the call's stream

@@ -51,6 +51,9 @@ enum GemmFlags : uint32_t {
   G_A_ZERO_UPPER = 32u,  // with G_A_LOWER: A's upper triangle is stored as zeros (no masking)
   G_A_UPPER = 64u,       // A upper triangular with zeros stored below the diagonal: the
                          // zero chunks are skipped (no masking)
+  G_C_LOWER = 128u,      // only the lower triangle of a square C (M == N, BM == BN) is
+                         // computed: tiles above the diagonal are not launched and elements
+                         // above it are left untouched (the symmetric rank-K update)
 };
 
 template <typename TIn, typename TCin, typename TCout, typename TC2>
@@ -105,7 +108,26 @@ __host__ __device__ inline bool tri_fold(int M, int K, uint32_t flags, int BM) {
 // Workgroups one product needs.
 __host__ __device__ inline int gemm_wgs(int M, int N, int K, uint32_t flags, int BM, int BN) {
   const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+  if (flags & G_C_LOWER) return ntm * (ntm + 1) / 2;
   return (tri_fold(M, K, flags, BM) ? (ntm + 1) / 2 : ntm) * ntn;
+}
+
+// Tile (tm, tn), tn <= tm, of workgroup `bid` among the t (t + 1) / 2 that
+// cover the lower triangle of a t x t tile grid.  Row tiles are paired, a
+// with t - 1 - a, so that a run of t + 1 consecutive ids covers one pair
+// (a + 1 tiles of row a, then t - a of row t - 1 - a); with a multiple of 8
+// workgroups the ids are regrouped so that each XCD takes a contiguous range
+// of pairs (they share their rows of A in its L2).
+__device__ __forceinline__ void lower_tile(int t, int bid, int nwg, int& tm, int& tn) {
+  if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  const int pr = bid / (t + 1), q = bid - pr * (t + 1);
+  if (q <= pr) {
+    tm = pr;
+    tn = q;
+  } else {
+    tm = t - 1 - pr;
+    tn = q - pr - 1;
+  }
 }
 
 // Row slot and column of workgroup `bid` among the nwg workgroups of one
@@ -212,6 +234,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout,
   Epi alpha = static_cast<Epi>(p.alpha);
   if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
   const Epi beta = static_cast<Epi>(p.beta);
+  const bool c_lower = p.flags & G_C_LOWER;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -223,7 +246,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmParams<TIn, TCin, TCout,
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = c0 + wn * WTN + j * 16 + gi;
-        if (col >= N) continue;
+        if (col >= N || (c_lower && col > row)) continue;
         epi_store(p, Co, Ci, row, col, static_cast<Epi>(acc[i][j][r]), alpha, beta, use_beta, rs);
       }
     }
@@ -268,7 +291,8 @@ __device__ __forceinline__ void gemm_epilogue_t(const GemmParams<TIn, TCin, TCou
   if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
   const Epi beta = static_cast<Epi>(p.beta);
   constexpr bool F32C = std::is_same<TCout, float>::value && std::is_same<TCin, float>::value;
-  const bool vec = F32C && !p.C2 &&
+  const bool c_lower = p.flags & G_C_LOWER;
+  const bool vec = F32C && !p.C2 && !c_lower &&
                    (((uintptr_t)Co | (uintptr_t)(Ci ? Ci : Co) | (uintptr_t)(p.ldco * 4) |
                      (uintptr_t)(p.ldci * 4)) & 15) == 0;
 #pragma unroll
@@ -298,7 +322,7 @@ __device__ __forceinline__ void gemm_epilogue_t(const GemmParams<TIn, TCin, TCou
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + r;
-        if (col < N)
+        if (col < N && !(c_lower && col > row))
           epi_store(p, Co, Ci, row, col, static_cast<Epi>(acc[i][j][r]), alpha, beta, use_beta, rs);
       }
     }
@@ -675,6 +699,16 @@ template <typename TIn, typename TCin, typename TCout, typename TC2,
 __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
                                           int s, int bid, int nwg) {
   const int ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
+  if (p.flags & G_C_LOWER) {
+    int tm, tn;
+    lower_tile(ntm, bid, nwg, tm, tn);
+    if constexpr (ALIGNED && !BKMAJOR && Mfma<TIn>::kPerLane == 1)
+      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, s, tm * BM, tn * BN);
+    else
+      gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, s, tm * BM,
+                                                                               tn * BN);
+    return;
+  }
   const bool fold = tri_fold(p.M, p.K, p.flags, BM);
   const bool uniform = fold || !(p.flags & (G_A_LOWER | G_B_LOWER | G_A_UPPER));
   const int rows = fold ? (ntm + 1) / 2 : ntm;
@@ -721,6 +755,7 @@ __global__ __launch_bounds__(256) void gemm_splitk_finish(GemmParams<TIn, TCin, 
     const int z = (int)(e / MN);
     const int64_t rc = e - z * MN;
     const int row = (int)(rc / p.N), col = (int)(rc - (int64_t)row * p.N);
+    if ((p.flags & G_C_LOWER) && col > row) continue;
     const Acc* q = P + (int64_t)z * p.ksplit * MN + rc;
     Acc v = q[0];
     for (int t = 1; t < p.ksplit; ++t) v += q[t * MN];
@@ -794,6 +829,7 @@ template <typename TIn, typename TCin, typename TCout, typename TC2,
 inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int batch,
                               hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
+  if ((p.flags & G_C_LOWER) && (p.M != p.N || BM != BN)) return hipErrorInvalidValue;
   const bool aligned = gemm_aligned<TIn, BM, BN, BKMAJOR>(p);
   const int64_t tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
   GemmParams<TIn, TCin, TCout, TC2> q = p;

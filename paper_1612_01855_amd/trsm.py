@@ -81,7 +81,8 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
            "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_poll",
-           "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy"]
+           "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy",
+           "trsm_chol_sizes", "trsm_chol_factor", "trsm_chol_check"]
 
 
 class TrsmError(RuntimeError):
@@ -158,6 +159,13 @@ def _load():
     lib.trsm_server_reset_stats.restype = i32
     lib.trsm_server_destroy.argtypes = [vp]
     lib.trsm_server_destroy.restype = i32
+    lib.trsm_chol_sizes.argtypes = [i64, i64, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.trsm_chol_sizes.restype = i32
+    lib.trsm_chol_factor.argtypes = [i64, vp, i64, i64, vp, vp, vp]
+    lib.trsm_chol_factor.restype = i32
+    lib.trsm_chol_check.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.trsm_chol_check.restype = i32
     return lib
 
 
@@ -331,6 +339,27 @@ def trsm_server_destroy(srv: int) -> None:
     _check(_lib.trsm_server_destroy(srv), "trsm_server_destroy")
 
 
+def trsm_chol_sizes(n: int, nb: int = 0):
+    """(nb_used, linv_bytes, workspace_bytes) of a Cholesky factorization."""
+    nbu, lb, wb = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.trsm_chol_sizes(n, nb, ctypes.byref(nbu), ctypes.byref(lb), ctypes.byref(wb)),
+           "trsm_chol_sizes")
+    return nbu.value, lb.value, wb.value
+
+
+def trsm_chol_factor(n: int, A: int, lda: int, nb: int, Linv: int, workspace: int,
+                     stream: int = 0) -> None:
+    _check(_lib.trsm_chol_factor(n, A, lda, nb, Linv, workspace, stream), "trsm_chol_factor")
+
+
+def trsm_chol_check(workspace: int):
+    """(status, index) of the last factorization on `workspace` (blocking)."""
+    st, idx = ctypes.c_int(), ctypes.c_int64()
+    _check(_lib.trsm_chol_check(workspace, ctypes.byref(st), ctypes.byref(idx)),
+           "trsm_chol_check")
+    return st.value, idx.value
+
+
 # ---- torch-tensor convenience (memory ownership only) ------------------------
 
 def _stream_handle(torch, device) -> int:
@@ -401,6 +430,61 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Cholesky:
+    """Owns the Linv and workspace buffers of a Cholesky factorization of one
+    size (torch uint8 tensors, 256-byte aligned views)."""
+
+    def __init__(self, n: int, nb: int = 0, device: str = "cuda"):
+        import torch
+        self.n = n
+        self.nb, lb, wb = trsm_chol_sizes(n, nb)
+        self._linv = torch.empty(max(lb, 1) + 256, dtype=torch.uint8, device=device)
+        self._ws = torch.empty(max(wb, 1) + 256, dtype=torch.uint8, device=device)
+        self.linv_bytes = lb
+
+    @property
+    def linv_ptr(self) -> int:
+        return (self._linv.data_ptr() + 255) // 256 * 256
+
+    @property
+    def workspace_ptr(self) -> int:
+        return (self._ws.data_ptr() + 255) // 256 * 256
+
+    def factor(self, A) -> None:
+        """In place: the lower triangle of the float64 tensor A becomes L."""
+        import torch
+        if A.dtype != torch.float64 or A.shape[0] != self.n or A.shape[1] < self.n:
+            raise ValueError("A must be an n x n float64 tensor")
+        trsm_chol_factor(self.n, A.data_ptr(), _ld(A), self.nb, self.linv_ptr,
+                         self.workspace_ptr, _stream_handle(torch, A.device))
+
+    def linv_blocks(self):
+        """The inverted diagonal blocks as an (m, nb, nb) float64 view."""
+        import torch
+        m = (self.n + self.nb - 1) // self.nb
+        off = self.linv_ptr - self._linv.data_ptr()
+        return self._linv[off:off + m * self.nb * self.nb * 8].view(torch.float64).view(
+            m, self.nb, self.nb)
+
+    def check(self):
+        return trsm_chol_check(self.workspace_ptr)
+
+
+def cholesky(A, nb: int = 0):
+    """L with A = L L^T on the GPU (A float64, symmetric positive definite;
+    only its lower triangle is read).  Returns a new tensor, zeros above the
+    diagonal; raises TrsmError(ESINGULAR) if A is not positive definite."""
+    import torch
+    n = A.shape[0]
+    L = A.clone()
+    c = Cholesky(n, nb, device=A.device)
+    c.factor(L)
+    st, idx = c.check()
+    if st != OK:
+        raise TrsmError(st, f"cholesky (row {idx})")
+    return L.tril_()
 
 
 def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None):

@@ -217,3 +217,39 @@ def test_transposed_plans(T):
                         (T.F64, T.FLAG_TRANSPOSE | T.FLAG_LOOKAHEAD)]:
         with pytest.raises(T.TrsmError):
             T.trsm_plan(300, 20, prec, 64, flags)
+
+
+def test_cholesky_sizes_and_validation_without_gpu(T):
+    # default block: min(256, next power of two >= max(n, 64))
+    assert T.trsm_chol_sizes(10)[0] == 64
+    assert T.trsm_chol_sizes(100)[0] == 128
+    assert T.trsm_chol_sizes(16384)[0] == 256
+    nb, lb, wb = T.trsm_chol_sizes(1000, 128)
+    m = (1000 + 127) // 128
+    assert nb == 128 and lb >= m * 128 * 128 * 8 and lb % 256 == 0
+    # status word + nb^2 temp + (n - nb) x nb panel + split-K scratch
+    assert wb >= 256 + 128 * 128 * 8 + (1000 - 128) * 128 * 8
+    # the Linv layout is a TRSM_F64 plan's with n0 = nb
+    p = T.trsm_plan(1000, 8, T.F64, 128, 0)
+    try:
+        assert T.trsm_plan_get_info(p).linv_bytes == lb
+    finally:
+        T.trsm_plan_destroy(p)
+    for bad_nb in (32, 96, 8192, -1):
+        with pytest.raises(T.TrsmError):
+            T.trsm_chol_sizes(100, bad_nb)
+    with pytest.raises(T.TrsmError):
+        T.trsm_chol_sizes(-1)
+    with pytest.raises(T.TrsmError):
+        T.trsm_chol_sizes((1 << 20) + 1)
+    lib = T._lib
+    fake = 1 << 20
+    # null A / Linv / workspace, lda < n, misaligned workspace or Linv
+    assert lib.trsm_chol_factor(64, None, 64, 0, fake, fake, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 64, 0, None, fake, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 64, 0, fake, None, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 63, 0, fake, fake, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 64, 0, fake, fake + 8, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 64, 0, fake + 8, fake, None) == T.EINVAL
+    assert lib.trsm_chol_factor(64, fake, 64, 48, fake, fake, None) == T.EINVAL
+    assert lib.trsm_chol_check(None, None, None) == T.EINVAL
