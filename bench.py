@@ -228,6 +228,45 @@ def time_solves(T, torch, dev, L64, B64, precision, n0, flags, reps, invert_each
     return float(np.median(times)), info, Xd
 
 
+def cholesky_bench(args, torch, T, gen, dev, emit):
+    """Blocked Cholesky A = L L^T (binary64) with the inverted-block panel
+    solve: median of 3 timed factorizations after a warm one, flops n^3 / 3,
+    and the backward error ||A - L L^T|| / ||A|| on 64 sampled rows."""
+    for n in (4096, 8192, 16384):
+        A0 = gen.spd_on(torch, dev, n, args.seed)
+        for nb in (0, 256, 512, 1024):
+            if nb > n // 4:
+                continue
+            c = T.Cholesky(n, nb, device=dev)
+            A = torch.empty_like(A0)
+            times = []
+            for it in range(4):
+                A.copy_(A0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                c.factor(A)
+                e1.record()
+                torch.cuda.synchronize()
+                if it:
+                    times.append(e0.elapsed_time(e1))
+            st, idx = c.check()
+            gcpu = torch.Generator().manual_seed(args.seed)
+            rows = torch.randint(0, n, (64,), generator=gcpu).to(dev)
+            L = torch.tril(A)
+            R = A0[rows] - L[rows] @ L.t()
+            be = float(torch.linalg.norm(R).item() / torch.linalg.norm(A0[rows]).item())
+            ms = sorted(times)[1]
+            tf = float(n) ** 3 / 3.0 / (ms * 1e-3) / 1e12
+            emit({"suite": "cholesky", "n": n, "nb": int(c.nb), "auto": nb == 0,
+                  "ms": round(ms, 3), "tflops_n3_3": round(tf, 2),
+                  "frac_peak": round(tf / PEAK["f64"], 4), "status": T.status_string(st),
+                  "sampled_backward_error": be})
+            log(f"suite cholesky n={n} nb={c.nb}: {ms:.2f} ms {tf:.2f} TF backward {be:.2e}")
+            del c, A, L, R
+        del A0
+        torch.cuda.empty_cache()
+
+
 def run_suite(args, torch, T, gen, dev):
     """The workload sweeps: n0 sweep and the recursive baseline at n = k = 8192
     (binary64 and binary32), the n/k sweep at n = 16384, and the hard factor in
@@ -322,6 +361,9 @@ def run_suite(args, torch, T, gen, dev):
           "rate_sweep": res.get("rate_sweep")})
     torch.cuda.empty_cache()
 
+    # blocked Cholesky factorization with the inverted-block panel solve
+    cholesky_bench(args, torch, T, gen, dev, emit)
+
     # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)
     n = k = 16384
     L64 = gen.chol_lower_on(torch, dev, n, args.seed, ratio=1e-12)
@@ -386,14 +428,20 @@ def main():
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--suite", action="store_true",
                     help="instead of the headline step, run the workload sweeps (one JSON line each)")
+    ap.add_argument("--cholesky", action="store_true",
+                    help="instead of the headline step, run only the Cholesky sweep of the suite")
     args = ap.parse_args()
 
-    if args.suite:
+    if args.suite or args.cholesky:
         import torch
         from paper_1612_01855_amd import inputs as gen
         from paper_1612_01855_amd import trsm as T
         assert torch.cuda.is_available(), "bench.py needs a GPU"
-        run_suite(args, torch, T, gen, torch.device("cuda:0"))
+        if args.cholesky:
+            cholesky_bench(args, torch, T, gen, torch.device("cuda:0"),
+                           lambda rec: print(json.dumps(rec), flush=True))
+        else:
+            run_suite(args, torch, T, gen, torch.device("cuda:0"))
         return
 
     if args.calibrate_copy:

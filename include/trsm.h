@@ -373,7 +373,7 @@ trsm_status trsm_server_destroy(trsm_server_t srv);
  * rows); then A(T_j, T_j) -= L(T_j, S_j) L(T_j, S_j)^T on the lower triangle.
  *
  * trsm_chol_sizes(n, nb, &nb_used, &linv_bytes, &workspace_bytes): host only.
- *  nb = 0 picks min(256, the next power of two >= max(n, 64)); otherwise nb
+ *  nb = 0 picks min(512, the next power of two >= max(n, 64)); otherwise nb
  *  must be a power of two in [64, 4096].  TRSM_EINVAL for n < 0, n > 2^20 or
  *  a bad nb.  Any output pointer may be NULL.
  * trsm_chol_factor(n, A, lda, nb, Linv, workspace, stream): A is a device
@@ -387,8 +387,14 @@ trsm_status trsm_server_destroy(trsm_server_t srv);
  *  L and these blocks directly (their values agree with trsm_invert_diag's
  *  up to rounding).  workspace: workspace_bytes of device memory, 256-byte
  *  aligned; its first 8 bytes hold the status word trsm_chol_check reads.
- *  Asynchronous on `stream`; no memory is allocated.  Returns TRSM_EINVAL for
- *  bad sizes, null or misaligned pointers.
+ *  Asynchronous; no memory is allocated.  With more than two blocks the
+ *  trailing updates below the next diagonal block run on a second stream
+ *  (created once per device by the library, default priority) while the
+ *  next diagonal block is factored on `stream`; events fork it from and join
+ *  it back to `stream`, so work enqueued on `stream` afterwards sees the
+ *  whole factorization, and the call can be captured into a graph on
+ *  `stream`.  Concurrent calls on one device are serialised while they
+ *  enqueue.  Returns TRSM_EINVAL for bad sizes, null or misaligned pointers.
  * trsm_chol_check(workspace, &status, &index): blocking (synchronises the
  *  device).  After trsm_chol_factor: TRSM_OK and -1, or TRSM_ESINGULAR and
  *  the first row whose pivot was not positive (A is not positive definite,

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/trsm.h"
 #include "common.hpp"
@@ -37,7 +38,7 @@ namespace trsm {
 namespace {
 
 constexpr int kLeaf = 64;
-constexpr int64_t kDefaultNb = 256;
+constexpr int64_t kDefaultNb = 512;
 constexpr int64_t kMaxNb = 4096;
 constexpr size_t kCholSplitBytes = (size_t)32 << 20;
 constexpr size_t kAl = 256;
@@ -49,68 +50,115 @@ inline int64_t pow2_at_least(int64_t v) {
   return p;
 }
 
+// Value of lane `lane` (a wave-uniform constant) for every lane.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Leaf: the s x s (s <= 64) diagonal block D (lower triangle read) is
-// factored in LDS, right-looking, column by column:
-//   l_jj = sqrt(d_jj);  l_ij = d_ij / l_jj;  d_ic -= l_ij l_cj  (j < c <= i),
-// then inverted by substitution on the identity (thread t owns column t of
-// the inverse).  L goes back to D's lower triangle (the strict upper triangle
-// is not written), the inverse to V (ld ldv; positions past s hold the
-// identity, and nothing above the diagonal is written).  A pivot that is not
-// positive (or NaN) records its global row in *bad (the smallest one wins)
-// and is replaced by 1 so that the arithmetic stays finite.
-__global__ __launch_bounds__(256) void chol_leaf_kernel(double* __restrict__ D, int64_t ldd,
-                                                        int s, double* __restrict__ V,
-                                                        int64_t ldv, int64_t row0,
-                                                        unsigned long long* bad) {
-  __shared__ double S[kLeaf][kLeaf + 1];
-  __shared__ double X[kLeaf][kLeaf + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < kLeaf * kLeaf; e += 256) {
-    const int i = e / kLeaf, j = e % kLeaf;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < s && j <= i) v = D[(int64_t)i * ldd + j];
-    S[i][j] = v;
-    X[i][j] = 0.0;
+// factored and inverted by ONE wave, lane i holding row i of the block in
+// registers (positions past s hold the identity).  Right-looking, step j:
+// every lane takes the pivot a_jj from lane j, then
+//   l_jj = sqrt(a_jj),  l_ij = a_ij / l_jj   (column j published in LDS),
+//   a_ic -= l_ij l_cj                        for c > j.
+// Entries above the diagonal are updated too (they are never read), so no
+// lane is masked.  The published columns form L column-major in LDS; lane t
+// then computes column t of the inverse by substitution on the identity,
+// x_rt = (delta_rt - sum_{p<r} l_rp x_pt) / l_rr (the sum with p ascending,
+// the division as a product with 1 / l_rr).  L goes back to D's lower
+// triangle (the strict upper triangle is not written), the inverse to V (ld
+// ldv; nothing above the diagonal is written).  A pivot that is not positive
+// (or NaN) records its global row in *bad (the smallest one wins) and is
+// replaced by 1 so that the arithmetic stays finite.  LDS reads come in
+// 16-byte pairs so that each step issues few of them.
+constexpr int kLdc = kLeaf + 2;   // column stride of Lc (16-byte aligned rows)
+constexpr int kAhead = 8;         // LDS pair reads in flight
+
+__global__ __launch_bounds__(kLeaf) void chol_leaf_kernel(double* __restrict__ D, int64_t ldd,
+                                                          int s, double* __restrict__ V,
+                                                          int64_t ldv, int64_t row0,
+                                                          unsigned long long* bad) {
+  __shared__ __attribute__((aligned(16))) double Lc[kLeaf][kLdc];
+  __shared__ double rdiag[kLeaf];
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  const int i = threadIdx.x;
+  // coalesced load (lane i takes column i of every row), staged in Lc
+  for (int r = 0; r < kLeaf; ++r) {
+    double v = (r == i) ? 1.0 : 0.0;
+    if (r < s && i <= r) v = D[(int64_t)r * ldd + i];
+    Lc[r][i] = v;
   }
   __syncthreads();
-  const int row = t % kLeaf, cg = t / kLeaf;
-  for (int j = 0; j < s; ++j) {
-    if (t == 0) {
-      double piv = S[j][j];
-      if (!(piv > 0.0)) {
-        atomicMin(bad, (unsigned long long)(row0 + j));
-        piv = 1.0;
-      }
-      S[j][j] = sqrt(piv);
-    }
-    __syncthreads();
-    if (t > j && t < s) S[t][j] = S[t][j] / S[j][j];
-    __syncthreads();
-    if (row > j && row < s) {
-      const double lij = S[row][j];
-      for (int c = j + 1 + cg; c <= row; c += 4) S[row][c] -= lij * S[c][j];
-    }
-    __syncthreads();
-  }
-  // inverse: x_tt = 1 / l_tt;  x_it = -(sum_{p<i} l_ip x_pt) / l_ii for i > t;
-  // every lane walks the same (i, p) so that l_ip is an LDS broadcast
-  if (t < kLeaf) {
-    X[t][t] = 1.0 / S[t][t];
-    for (int i = 1; i < kLeaf; ++i) {
-      if (t < i) {
-        double acc = 0.0;
-        for (int p = 0; p < i; ++p) acc += S[i][p] * X[p][t];
-        X[i][t] = -acc / S[i][i];
-      }
-    }
+  double a[kLeaf];
+#pragma unroll
+  for (int c = 0; c < kLeaf; c += 2) {
+    const D2 v = *reinterpret_cast<const D2*>(&Lc[i][c]);
+    a[c] = v.x;
+    a[c + 1] = v.y;
   }
   __syncthreads();
-  for (int e = t; e < kLeaf * kLeaf; e += 256) {
-    const int i = e / kLeaf, j = e % kLeaf;
-    if (j > i) continue;
-    if (i < s) D[(int64_t)i * ldd + j] = S[i][j];
-    V[(int64_t)i * ldv + j] = X[i][j];
+  // the loop is kept free of branches (they split it into blocks that the
+  // register allocator handles badly): failures are collected in `first`
+  int first = kLeaf;
+#pragma unroll
+  for (int j = 0; j < kLeaf; ++j) {
+    double piv = lane_value(a[j], j);
+    const bool ok = piv > 0.0;
+    first = (!ok && first == kLeaf) ? j : first;
+    piv = ok ? piv : 1.0;
+    const double d = sqrt(piv);
+    const double l = (i == j) ? d : a[j] / d;
+    a[j] = l;
+    Lc[j][i] = l;
+    rdiag[j] = 1.0 / d;
+    __syncthreads();
+    // pairs q = c / 2 from the one holding column j + 1; each read is
+    // issued kAhead pairs before its use
+    const int q0 = (j + 1) / 2;
+    D2 buf[kLeaf / 2];
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
+      buf[q] = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2; ++q) {
+      if (q + kAhead < kLeaf / 2) buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[j][2 * (q + kAhead)]);
+      if (2 * q > j) a[2 * q] = fma(-l, buf[q].x, a[2 * q]);
+      a[2 * q + 1] = fma(-l, buf[q].y, a[2 * q + 1]);
+    }
   }
+  if (i == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
+  __syncthreads();
+  // L back to D, rows coalesced: element (r, i) is Lc[i][r]
+  for (int r = 0; r < s; ++r)
+    if (i <= r) D[(int64_t)r * ldd + i] = Lc[i][r];
+  double x[kLeaf];
+#pragma unroll
+  for (int r = 0; r < kLeaf; ++r) x[r] = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < kLeaf; ++j) {
+    x[j] *= rdiag[j];
+    const int q0 = (j + 1) / 2;
+    D2 buf[kLeaf / 2];
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
+      buf[q] = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2; ++q) {
+      if (q + kAhead < kLeaf / 2) buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[j][2 * (q + kAhead)]);
+      if (2 * q > j) x[2 * q] = fma(-buf[q].x, x[j], x[2 * q]);
+      x[2 * q + 1] = fma(-buf[q].y, x[j], x[2 * q + 1]);
+    }
+  }
+  // column i of the inverse through LDS, then coalesced rows (r >= i)
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kLeaf; ++r) Lc[r][i] = x[r];
+  __syncthreads();
+  for (int r = 0; r < kLeaf; ++r)
+    if (i <= r) V[(int64_t)r * ldv + i] = Lc[r][i];
 }
 
 // Linv blocks: zero everywhere except the identity on the padded diagonal of
@@ -131,7 +179,7 @@ struct Ctx {
   int64_t lda, n, nb;
   double* V;      // m inverted diagonal blocks, nb x nb each
   double* W;      // nb x nb: the diagonal block's panel and combine
-  double* W2;     // (n - nb) x nb: the outer panel L(T_j, S_j)
+  double* W2[2];  // (n - nb) x nb each: the outer panel L(T_j, S_j), by parity of j
   void* split;    // split-K scratch
   size_t split_bytes;
   unsigned long long* bad;
@@ -140,11 +188,13 @@ struct Ctx {
 
 // C = alpha * A op(B) (+ C when accumulate); op(B) = B^T stored as N x K rows
 // when BT.  Products with fewer than two 128 x 128 workgroups per compute
-// unit take 64 x 64 tiles (and split K when still small).
+// unit take 64 x 64 tiles (and split K when still small, if `split`: the
+// products inside a diagonal block are too small for the finishing pass to
+// pay off).
 template <bool BT>
 hipError_t prod(const Ctx& c, const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha,
-                bool accumulate, uint32_t flags) {
+                bool accumulate, uint32_t flags, bool split = true) {
   auto p = gemm_params<double, double, double, float>();
   p.A = A; p.lda = lda;
   p.B = B; p.ldb = ldb;
@@ -158,8 +208,8 @@ hipError_t prod(const Ctx& c, const double* A, int64_t lda, const double* B, int
   p.M = (int)M; p.N = (int)N; p.K = (int)K;
   p.alpha = alpha;
   p.flags = flags;
-  p.part = c.split;
-  p.part_bytes = (int64_t)c.split_bytes;
+  p.part = split ? c.split : nullptr;
+  p.part_bytes = split ? (int64_t)c.split_bytes : 0;
   const bool small = gemm_wgs(p.M, p.N, p.K, flags, 128, 128) < kSplitTarget;
   return small ? launch_gemm<double, double, double, float, 64, 64, 2, 2, BT>(p, 1, c.s)
                : launch_gemm<double, double, double, float, 128, 128, 2, 2, BT>(p, 1, c.s);
@@ -183,7 +233,7 @@ trsm_status factor_diag(const Ctx& c, int64_t r0, int64_t s, double* V) {
   const int64_t lda = c.lda, nb = c.nb;
   double* D = c.A + r0 * lda + r0;
   if (s <= kLeaf) {
-    chol_leaf_kernel<<<1, 256, 0, c.s>>>(D, lda, (int)s, V, nb, r0, c.bad);
+    chol_leaf_kernel<<<1, kLeaf, 0, c.s>>>(D, lda, (int)s, V, nb, r0, c.bad);
     CHOL_HIP(hipGetLastError());
     return TRSM_OK;
   }
@@ -194,27 +244,66 @@ trsm_status factor_diag(const Ctx& c, int64_t r0, int64_t s, double* V) {
   double* V21 = V + h * nb;
   double* V22 = V21 + h;
   CHOL_TRY(factor_diag(c, r0, h, V));
-  // L21 = D21 Linv11^T (into W, then back into D21)
-  CHOL_HIP(prod<true>(c, D21, lda, V, nb, c.W, nb, t, h, h, 1.0, false, 0u));
-  CHOL_HIP(launch_copy2d<double, double>(c.W, nb, D21, lda, t, h, 1.0, c.s));
+  // L21 = D21 Linv11^T.  With h <= 64 the product has one column tile, so
+  // each workgroup reads its rows of D21 in full before it writes them and
+  // the product runs in place; otherwise it goes through W.
+  const double* L21 = D21;
+  int64_t ld21 = lda;
+  if (h <= kLeaf) {
+    CHOL_HIP(prod<true>(c, D21, lda, V, nb, D21, lda, t, h, h, 1.0, false, 0u, false));
+  } else {
+    CHOL_HIP(prod<true>(c, D21, lda, V, nb, c.W, nb, t, h, h, 1.0, false, 0u, false));
+    CHOL_HIP(launch_copy2d<double, double>(c.W, nb, D21, lda, t, h, 1.0, c.s));
+    L21 = c.W;
+    ld21 = nb;
+  }
   // D22 -= L21 L21^T, lower triangle
-  CHOL_HIP(prod<true>(c, c.W, nb, c.W, nb, D22, lda, t, t, h, -1.0, true, G_C_LOWER));
+  CHOL_HIP(prod<true>(c, L21, ld21, L21, ld21, D22, lda, t, t, h, -1.0, true, G_C_LOWER, false));
   CHOL_TRY(factor_diag(c, r0 + h, t, V22));
   // Linv21 = -(Linv22 L21) Linv11
   CHOL_HIP(prod<false>(c, V22, nb, D21, lda, c.W, nb, t, h, t, 1.0, false,
-                       G_A_LOWER | G_A_ZERO_UPPER));
-  CHOL_HIP(prod<false>(c, c.W, nb, V, nb, V21, nb, t, h, h, -1.0, false, G_B_LOWER));
+                       G_A_LOWER | G_A_ZERO_UPPER, false));
+  CHOL_HIP(prod<false>(c, c.W, nb, V, nb, V21, nb, t, h, h, -1.0, false, G_B_LOWER, false));
   return TRSM_OK;
 }
 
-trsm_status factor(const Ctx& c) {
-  const int64_t n = c.n, nb = c.nb, m = (n + nb - 1) / nb, lda = c.lda;
-  {
-    const int64_t total = m * nb * nb;
-    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-    chol_init_kernel<<<g, 256, 0, c.s>>>(c.V, n, nb, m, c.bad);
-    CHOL_HIP(hipGetLastError());
+// The library's second stream and its events, per device: the lookahead
+// runs the bulk of each trailing update there.  Enqueueing is serialised by
+// the mutex (the events are reused from one step to the next: a wait takes
+// the event's state at the moment it is enqueued).
+struct Side {
+  std::mutex mu;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+constexpr int kMaxDevices = 64;
+Side g_side[kMaxDevices];
+
+trsm_status side_for(Side** out) {
+  int dev = 0;
+  CHOL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TRSM_EINVAL;
+  Side& sd = g_side[dev];
+  if (!sd.s2) {
+    CHOL_HIP(hipStreamCreateWithFlags(&sd.s2, hipStreamNonBlocking));
+    for (auto& e : sd.ev) CHOL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  *out = &sd;
+  return TRSM_OK;
+}
+
+trsm_status init(const Ctx& c, int64_t m) {
+  const int64_t total = m * c.nb * c.nb;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+  chol_init_kernel<<<g, 256, 0, c.s>>>(c.V, c.n, c.nb, m, c.bad);
+  CHOL_HIP(hipGetLastError());
+  return TRSM_OK;
+}
+
+// One stream: diagonal block, panel, trailing update, in order.
+trsm_status factor_serial(const Ctx& c) {
+  const int64_t n = c.n, nb = c.nb, m = (n + nb - 1) / nb, lda = c.lda;
+  CHOL_TRY(init(c, m));
   for (int64_t j = 0; j < m; ++j) {
     const int64_t r0 = j * nb, s = std::min(nb, n - r0), t = n - r0 - s;
     double* Vj = c.V + j * nb * nb;
@@ -223,17 +312,73 @@ trsm_status factor(const Ctx& c) {
     double* A21 = c.A + (r0 + s) * lda + r0;
     double* A22 = A21 + s;
     // L(T_j, S_j) = A(T_j, S_j) Linv_jj^T
-    CHOL_HIP(prod<true>(c, A21, lda, Vj, nb, c.W2, nb, t, s, s, 1.0, false, 0u));
-    CHOL_HIP(launch_copy2d<double, double>(c.W2, nb, A21, lda, t, s, 1.0, c.s));
+    CHOL_HIP(prod<true>(c, A21, lda, Vj, nb, c.W2[0], nb, t, s, s, 1.0, false, 0u));
+    CHOL_HIP(launch_copy2d<double, double>(c.W2[0], nb, A21, lda, t, s, 1.0, c.s));
     // A(T_j, T_j) -= L(T_j, S_j) L(T_j, S_j)^T, lower triangle
-    CHOL_HIP(prod<true>(c, c.W2, nb, c.W2, nb, A22, lda, t, t, s, -1.0, true, G_C_LOWER));
+    CHOL_HIP(prod<true>(c, c.W2[0], nb, c.W2[0], nb, A22, lda, t, t, s, -1.0, true, G_C_LOWER));
   }
+  return TRSM_OK;
+}
+
+// Lookahead over two streams.  Update j, A(T_j, T_j) -= P_j P_j^T, is split
+// into the next diagonal block A(S_{j+1}, S_{j+1}) (on the caller's stream,
+// the critical chain) and everything below it, A(T_{j+1}, S_{j+1} u T_{j+1})
+// (on the side stream).  The side part of update j runs while the chain
+// factors diagonal block j+1, whose inputs are complete once the chain's own
+// part of update j is done (the side parts of earlier updates, which also
+// touched that block, were finished before panel j).  Panel j+1 then waits
+// for the side part of update j (event 2), which wrote the rows it reads;
+// the side part of update j+1 waits for panel j+1 (event 1).  Panels
+// alternate between two buffers, so panel j+1 never overwrites the one the
+// side stream may still be reading.
+trsm_status factor_lookahead(const Ctx& c, Side& sd) {
+  const int64_t n = c.n, nb = c.nb, m = (n + nb - 1) / nb, lda = c.lda;
+  hipStream_t s2 = sd.s2;
+  Ctx c2 = c;
+  c2.s = s2;
+  c2.split = nullptr;
+  c2.split_bytes = 0;
+  CHOL_TRY(init(c, m));
+  CHOL_HIP(hipEventRecord(sd.ev[0], c.s));
+  CHOL_HIP(hipStreamWaitEvent(s2, sd.ev[0], 0));
+  bool pending = false;
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t r0 = j * nb, s = std::min(nb, n - r0), t = n - r0 - s;
+    double* Vj = c.V + j * nb * nb;
+    CHOL_TRY(factor_diag(c, r0, s, Vj));
+    if (t <= 0) break;
+    double* P = c.W2[j & 1];
+    double* A21 = c.A + (r0 + s) * lda + r0;
+    double* A22 = A21 + s;
+    if (pending) CHOL_HIP(hipStreamWaitEvent(c.s, sd.ev[2], 0));
+    CHOL_HIP(prod<true>(c, A21, lda, Vj, nb, P, nb, t, s, s, 1.0, false, 0u));
+    CHOL_HIP(launch_copy2d<double, double>(P, nb, A21, lda, t, s, 1.0, c.s));
+    const int64_t s1 = std::min(nb, t);
+    // the next diagonal block, lower triangle, on the chain
+    CHOL_HIP(prod<true>(c, P, nb, P, nb, A22, lda, s1, s1, s, -1.0, true, G_C_LOWER));
+    if (t > s1) {
+      CHOL_HIP(hipEventRecord(sd.ev[1], c.s));
+      CHOL_HIP(hipStreamWaitEvent(s2, sd.ev[1], 0));
+      // rows T_{j+1}: block column S_{j+1}, then the lower triangle of T_{j+1}
+      CHOL_HIP(prod<true>(c2, P + s1 * nb, nb, P, nb, A22 + s1 * lda, lda, t - s1, s1, s, -1.0,
+                          true, 0u));
+      CHOL_HIP(prod<true>(c2, P + s1 * nb, nb, P + s1 * nb, nb, A22 + s1 * lda + s1, lda,
+                          t - s1, t - s1, s, -1.0, true, G_C_LOWER));
+      CHOL_HIP(hipEventRecord(sd.ev[2], s2));
+      pending = true;
+    } else {
+      pending = false;
+    }
+  }
+  // join: the caller's stream sees the side stream's work
+  CHOL_HIP(hipEventRecord(sd.ev[2], s2));
+  CHOL_HIP(hipStreamWaitEvent(c.s, sd.ev[2], 0));
   return TRSM_OK;
 }
 
 struct Sizes {
   int64_t nb;
-  size_t linv, off_w, off_w2, off_split, ws;
+  size_t linv, off_w, off_w2, w2_bytes, off_split, ws;
 };
 
 trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z) {
@@ -248,7 +393,8 @@ trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z) {
   z->off_w = off;
   off += al((size_t)nb * nb * 8);
   z->off_w2 = off;
-  off += al((size_t)std::max<int64_t>(n - nb, 1) * nb * 8);
+  z->w2_bytes = al((size_t)std::max<int64_t>(n - nb, 1) * nb * 8);
+  off += 2 * al((size_t)std::max<int64_t>(n - nb, 1) * nb * 8);
   z->off_split = off;
   off += kCholSplitBytes;
   z->ws = off;
@@ -288,7 +434,8 @@ trsm_status trsm_chol_factor(int64_t n, double* A, int64_t lda, int64_t nb, doub
   char* w = static_cast<char*>(workspace);
   c.bad = reinterpret_cast<unsigned long long*>(w);
   c.W = reinterpret_cast<double*>(w + z.off_w);
-  c.W2 = reinterpret_cast<double*>(w + z.off_w2);
+  c.W2[0] = reinterpret_cast<double*>(w + z.off_w2);
+  c.W2[1] = reinterpret_cast<double*>(w + z.off_w2 + z.w2_bytes);
   c.split = w + z.off_split;
   c.split_bytes = kCholSplitBytes;
   c.s = static_cast<hipStream_t>(stream);
@@ -297,7 +444,12 @@ trsm_status trsm_chol_factor(int64_t n, double* A, int64_t lda, int64_t nb, doub
     CHOL_HIP(hipGetLastError());
     return TRSM_OK;
   }
-  return factor(c);
+  // the lookahead pays once there are a few blocks to overlap
+  if ((n + z.nb - 1) / z.nb <= 2) return factor_serial(c);
+  Side* sd = nullptr;
+  CHOL_TRY(side_for(&sd));
+  std::lock_guard<std::mutex> g(sd->mu);
+  return factor_lookahead(c, *sd);
 }
 
 trsm_status trsm_chol_check(const void* workspace, trsm_status* status, int64_t* index) {

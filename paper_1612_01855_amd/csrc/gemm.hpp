@@ -337,18 +337,21 @@ constexpr int vmcnt_imm(int n) {
 
 // Matrix-core tile with operands copied from HBM straight into LDS by
 // buffer loads (no register staging), two LDS stages, one barrier per chunk.
-// For one-k-per-lane instructions (binary64, binary32) with row-major B and
-// 16-byte aligned operands.  LDS layout per stage:
+// For one-k-per-lane instructions (binary64, binary32) and 16-byte aligned
+// operands.  LDS layout per stage:
 //  * A: BM rows of 128 bytes (BK elements), the eight 16-byte pieces of row r
 //    stored XOR-swizzled (piece d at position d ^ (r & 7)), so that the 16
 //    rows a fragment read touches fall in different banks;
-//  * B: BK rows of BN elements; each wave load instruction writes 1 KB (one
-//    or more whole rows) and is followed by 16 bytes of padding.
+//  * B, row-major (BKMAJOR false): BK rows of BN elements; each wave load
+//    instruction writes 1 KB (one or more whole rows) and is followed by 16
+//    bytes of padding;
+//  * B given as B^T (BKMAJOR true: N rows of K, k contiguous): BN rows of
+//    128 bytes swizzled like A, and read like A.
 // All fragments of a half-chunk are read before its MFMAs are issued.
 // Triangular masks are applied to the fragments, only in chunks that cross
 // the diagonal.
 template <typename TIn, typename TCin, typename TCout, typename TC2, int BM, int BN, int WGM,
-          int WGN>
+          int WGN, bool BKMAJOR = false>
 __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
                                               int s, const int r0, const int c0) {
   using MF = Mfma<TIn>;
@@ -366,13 +369,15 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
   constexpr int ROW_B = BN * ES;                 // bytes of one B row
   constexpr int RPI = 1024 / ROW_B;              // B rows per wave instruction
   constexpr int B_INST_TOTAL = BK / RPI;
-  constexpr int B_BYTES = B_INST_TOTAL * (1024 + 16);
+  constexpr int B_BYTES = BKMAJOR ? BN * 128 : B_INST_TOTAL * (1024 + 16);
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int A_INST = BM / 8 / NW;
   constexpr int B_INST = B_INST_TOTAL / NW;
+  constexpr int BT_INST = BN / 8 / NW;
   static_assert(MF::kPerLane == 1, "one k per lane");
   static_assert(RPI * ROW_B == 1024, "a wave instruction must cover whole B rows");
   static_assert(A_INST * NW * 8 == BM && B_INST * NW == B_INST_TOTAL, "even split of loads");
+  static_assert(!BKMAJOR || BT_INST * NW * 8 == BN, "even split of B^T loads");
   __shared__ __attribute__((aligned(1024))) char smem[2 * STAGE];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -410,6 +415,21 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           ra, (__attribute__((address_space(3))) void*)(base + rb * 128), 16, off, 0, 0, 0);
     }
+    if constexpr (BKMAJOR) {
+      const __amdgpu_buffer_rsrc_t rbt = make_rsrc(B + (int64_t)c0 * ldb + k0);
+#pragma unroll
+      for (int q = 0; q < BT_INST; ++q) {
+        const int rb = 8 * (wave * BT_INST + q);
+        const int r = rb + (lane >> 3);
+        const int d = (lane & 7) ^ (r & 7);
+        const bool ok = (c0 + r < N) && (k0 + d * VEC < K);
+        const int off = ok ? (r * ldb + d * VEC) * ES : kBufOOB;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rbt, (__attribute__((address_space(3))) void*)(base + A_BYTES + rb * 128), 16, off, 0,
+            0, 0);
+      }
+      return;
+    }
     const __amdgpu_buffer_rsrc_t rbs = make_rsrc(B + (int64_t)k0 * ldb + c0);
 #pragma unroll
     for (int q = 0; q < B_INST; ++q) {
@@ -444,14 +464,25 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams<TIn, TCin, TCout,
         const int slot = (2 * g + h) ^ (r & 7);
         fa[i] = *reinterpret_cast<const V16*>(as + r * 128 + slot * 16);
       }
+      if constexpr (BKMAJOR) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int kr = g * KL + h * VEC + e;
+        for (int j = 0; j < TN; ++j) {
+          const int r = wn * WTN + j * 16 + gi;
+          const int slot = (2 * g + h) ^ (r & 7);
+          const V16 v = *reinterpret_cast<const V16*>(bs + r * 128 + slot * 16);
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          fb[e][j] = *reinterpret_cast<const TIn*>(bs + (kr / RPI) * (1024 + 16) +
-                                                   (kr % RPI) * ROW_B +
-                                                   (wn * WTN + j * 16 + gi) * ES);
+          for (int e = 0; e < VEC; ++e) fb[e][j] = v[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const int kr = g * KL + h * VEC + e;
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            fb[e][j] = *reinterpret_cast<const TIn*>(bs + (kr / RPI) * (1024 + 16) +
+                                                     (kr % RPI) * ROW_B +
+                                                     (wn * WTN + j * 16 + gi) * ES);
+        }
       }
       if (mask_a) {
 #pragma unroll
@@ -694,16 +725,16 @@ __device__ __forceinline__ void gemm_tile_staged(const GemmParams<TIn, TCin, TCo
 // The output tiles of workgroup `bid` (of nwg) of one batch entry z: one
 // tile, or two for a folded triangular product.
 template <typename TIn, typename TCin, typename TCout, typename TC2,
-          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED,
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED, bool CLOWER = false,
           int GROUP_M = 8, bool XCD_REMAP = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2>& p, int z,
                                           int s, int bid, int nwg) {
   const int ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
-  if (p.flags & G_C_LOWER) {
+  if constexpr (CLOWER) {
     int tm, tn;
     lower_tile(ntm, bid, nwg, tm, tn);
-    if constexpr (ALIGNED && !BKMAJOR && Mfma<TIn>::kPerLane == 1)
-      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, s, tm * BM, tn * BN);
+    if constexpr (ALIGNED && Mfma<TIn>::kPerLane == 1)
+      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR>(p, z, s, tm * BM, tn * BN);
     else
       gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, s, tm * BM,
                                                                                tn * BN);
@@ -715,8 +746,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
   int slot, tn;
   tile_slot<GROUP_M, XCD_REMAP>(rows, ntn, uniform, bid, nwg, slot, tn);
   auto one = [&](int tm) {
-    if constexpr (ALIGNED && !BKMAJOR && Mfma<TIn>::kPerLane == 1)
-      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN>(p, z, s, tm * BM, tn * BN);
+    if constexpr (ALIGNED && Mfma<TIn>::kPerLane == 1)
+      gemm_tile_dma<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR>(p, z, s, tm * BM, tn * BN);
     else
       gemm_tile_staged<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, z, s, tm * BM,
                                                                                tn * BN);
@@ -729,11 +760,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<TIn, TCin, TCout, TC2
 }
 
 template <typename TIn, typename TCin, typename TCout, typename TC2,
-          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
+          int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED, bool CLOWER = false>
 __global__ __launch_bounds__(WGM * WGN * 64, 2)
 void gemm_kernel(GemmParams<TIn, TCin, TCout, TC2> p) {
-  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, blockIdx.z, blockIdx.y,
-                                                                      blockIdx.x, gridDim.x);
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED, CLOWER>(
+      p, blockIdx.z, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // Split-K finish: the fixed-order sum of the ksplit partial products of
@@ -837,12 +868,22 @@ inline hipError_t launch_gemm(const GemmParams<TIn, TCin, TCout, TC2>& p, int ba
   // four for the smaller ones (their registers and LDS allow it)
   const int target = (BM * BN >= 128 * 128) ? kSplitTarget : 2 * kSplitTarget;
   q.ksplit = gemm_ksplit<TIn>(p, tiles * batch, batch, target);
+  // lower-triangle products take their own instantiation (tile enumeration)
+  const bool clower = p.flags & G_C_LOWER;
   dim3 grid((unsigned)tiles, (unsigned)q.ksplit, (unsigned)batch);
   dim3 block(WGM * WGN * 64);
-  if (aligned)
+  if (clower) {
+    if (aligned)
+      gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, true, true>
+          <<<grid, block, 0, stream>>>(q);
+    else
+      gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, false, true>
+          <<<grid, block, 0, stream>>>(q);
+  } else if (aligned) {
     gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, true><<<grid, block, 0, stream>>>(q);
-  else
+  } else {
     gemm_kernel<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, false><<<grid, block, 0, stream>>>(q);
+  }
   if (q.ksplit > 1) {
     const int64_t total = (int64_t)p.M * p.N * batch;
     const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);

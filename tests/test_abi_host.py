@@ -220,15 +220,15 @@ def test_transposed_plans(T):
 
 
 def test_cholesky_sizes_and_validation_without_gpu(T):
-    # default block: min(256, next power of two >= max(n, 64))
+    # default block: min(512, next power of two >= max(n, 64))
     assert T.trsm_chol_sizes(10)[0] == 64
     assert T.trsm_chol_sizes(100)[0] == 128
-    assert T.trsm_chol_sizes(16384)[0] == 256
+    assert T.trsm_chol_sizes(16384)[0] == 512
     nb, lb, wb = T.trsm_chol_sizes(1000, 128)
     m = (1000 + 127) // 128
     assert nb == 128 and lb >= m * 128 * 128 * 8 and lb % 256 == 0
-    # status word + nb^2 temp + (n - nb) x nb panel + split-K scratch
-    assert wb >= 256 + 128 * 128 * 8 + (1000 - 128) * 128 * 8
+    # status word + nb^2 temp + two (n - nb) x nb panels + split-K scratch
+    assert wb >= 256 + 128 * 128 * 8 + 2 * (1000 - 128) * 128 * 8
     # the Linv layout is a TRSM_F64 plan's with n0 = nb
     p = T.trsm_plan(1000, 8, T.F64, 128, 0)
     try:
