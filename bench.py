@@ -232,9 +232,11 @@ def cholesky_bench(args, torch, T, gen, dev, emit):
     """Blocked Cholesky A = L L^T (binary64) with the inverted-block panel
     solve: median of 3 timed factorizations after a warm one, flops n^3 / 3,
     and the backward error ||A - L L^T|| / ||A|| on 64 sampled rows."""
-    for n in (4096, 8192, 16384):
+    sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
+    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512, 1024)
+    for n in sizes:
         A0 = gen.spd_on(torch, dev, n, args.seed)
-        for nb in (0, 256, 512, 1024):
+        for nb in blocks:
             if nb > n // 4:
                 continue
             c = T.Cholesky(n, nb, device=dev)
@@ -430,6 +432,8 @@ def main():
                     help="instead of the headline step, run the workload sweeps (one JSON line each)")
     ap.add_argument("--cholesky", action="store_true",
                     help="instead of the headline step, run only the Cholesky sweep of the suite")
+    ap.add_argument("--chol-n", type=int, default=0, help="--cholesky: this n only")
+    ap.add_argument("--chol-nb", type=int, default=None, help="--cholesky: this block size only")
     args = ap.parse_args()
 
     if args.suite or args.cholesky:
