@@ -212,3 +212,52 @@ def test_transposed_f64_n16384_k16384(torch, T):
     err = oracle.rel_fro_err(Xs, oracle.trsm_t(L, np.ascontiguousarray(B[:, cols])))
     log(f"full size transposed f64: sampled rel err {err:.2e}")
     assert err <= TOL64
+
+
+@pytest.mark.parametrize("ratio", [None, 1e-12])
+def test_cholesky_factor_n16384(torch, T, ratio):
+    """The blocked Cholesky factorization at n = 16384 in the benchmark's
+    configuration (default block size), checked by properties the oracle can
+    evaluate one piece at a time: the leading 1024 x 1024 block of L is the
+    factor of A's leading block (the oracle factors it); sampled rows of L
+    satisfy their defining equation L(i, 0:i) = L(0:i, 0:i)^{-1} A(0:i, i) and
+    l_ii^2 = a_ii - |L(i, 0:i)|^2 (the oracle's substitution); a sampled
+    inverted diagonal block is the inverse of L's block (oracle); and the
+    backward error of sampled rows of A - L L^T."""
+    n = 16384
+    A0 = gen.spd_on(torch, "cuda", n, 17, ratio=ratio)
+    A0 = torch.tril(A0) + torch.tril(A0, -1).t()          # exactly symmetric
+    Ad = A0.clone()
+    c = T.Cholesky(n, 0, device="cuda")
+    c.factor(Ad)
+    torch.cuda.synchronize()
+    assert c.check() == (T.OK, -1)
+    tol = TOL64 if ratio is None else 1e-9     # L's forward error grows with cond(A)
+    lead = 1024
+    Lref, f = oracle.chol(A0[:lead, :lead].cpu().numpy())
+    err = oracle.rel_fro_err(np.tril(Ad[:lead, :lead].cpu().numpy()), Lref)
+    log(f"full size cholesky ratio={ratio}: leading block rel err {err:.2e}")
+    assert f == -1 and err <= tol
+    rows = np.sort(np.random.default_rng(3).choice(np.arange(lead, n), 6, replace=False))
+    for i in rows:
+        Li = Ad[:i, :i].cpu().numpy()
+        a = A0[:i, i].cpu().numpy()[:, None]
+        x = oracle.trsm(Li, a)[:, 0]
+        row = Ad[i, :i].cpu().numpy()
+        e = np.linalg.norm(row - x) / np.linalg.norm(x)
+        lii = float(Ad[i, i].item())
+        aii = float(A0[i, i].item())
+        d = abs(lii * lii + float(np.dot(row, row)) - aii) / aii
+        log(f"  row {i}: rel err {e:.2e}, diagonal {d:.2e}")
+        assert e <= tol and d <= tol
+    j = 17
+    nb = c.nb
+    blk = c.linv_blocks()[j].cpu().numpy()
+    inv = oracle.inv_lower(np.tril(Ad[j * nb:(j + 1) * nb, j * nb:(j + 1) * nb].cpu().numpy()))
+    assert oracle.rel_fro_err(blk, inv) <= tol
+    idx = torch.from_numpy(np.sort(np.random.default_rng(5).choice(n, 64, replace=False))).cuda()
+    L = torch.tril(Ad)
+    R = A0.index_select(0, idx) - L.index_select(0, idx) @ L.t()
+    be = float(torch.linalg.norm(R).item() / torch.linalg.norm(A0.index_select(0, idx)).item())
+    log(f"  sampled backward error {be:.2e}")
+    assert be <= 4 * n * 2.0 ** -53
