@@ -59,52 +59,72 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 }
 
 // Leaf: the s x s (s <= 64) diagonal block D (lower triangle read) is
-// factored and inverted by ONE wave, lane i holding row i of the block in
-// registers (positions past s hold the identity).  Right-looking, step j:
-// every lane takes the pivot a_jj from lane j, then
+// factored by wave 0 and inverted by wave 1, one step behind it.  Wave 0,
+// lane i holding row i of the block in registers (positions past s hold the
+// identity), right-looking, step j: every lane takes the pivot a_jj from
+// lane j, then
 //   l_jj = sqrt(a_jj),  l_ij = a_ij / l_jj   (column j published in LDS),
 //   a_ic -= l_ij l_cj                        for c > j.
 // Entries above the diagonal are updated too (they are never read), so no
-// lane is masked.  The published columns form L column-major in LDS; lane t
-// then computes column t of the inverse by substitution on the identity,
-// x_rt = (delta_rt - sum_{p<r} l_rp x_pt) / l_rr (the sum with p ascending,
-// the division as a product with 1 / l_rr).  L goes back to D's lower
-// triangle (the strict upper triangle is not written), the inverse to V (ld
-// ldv; nothing above the diagonal is written).  A pivot that is not positive
-// (or NaN) records its global row in *bad (the smallest one wins) and is
-// replaced by 1 so that the arithmetic stays finite.  LDS reads come in
-// 16-byte pairs so that each step issues few of them.
+// lane is masked.  Wave 1, lane t holding column t of the inverse (starting
+// from the identity), takes column j of L from LDS in the next step:
+//   x_jt *= 1 / l_jj,   x_rt -= l_rj x_jt   for r > j,
+// i.e. x_rt = (delta_rt - sum_{p<r} l_rp x_pt) / l_rr with the sum taken in
+// p order.  The two waves share one register array (each uses it for its
+// own role).  L goes back to D's lower triangle (the strict upper triangle
+// is not written), the inverse to V (ld ldv; nothing above the diagonal is
+// written).  A pivot that is not positive (or NaN) records its global row in
+// *bad (the smallest one wins) and is replaced by 1 so that the arithmetic
+// stays finite.  LDS reads come in 16-byte pairs issued ahead of their use.
 constexpr int kLdc = kLeaf + 2;   // column stride of Lc (16-byte aligned rows)
 constexpr int kAhead = 8;         // LDS pair reads in flight
+constexpr int kGroup = 8;         // leaf steps between the two waves' barriers
 
-__global__ __launch_bounds__(kLeaf) void chol_leaf_kernel(double* __restrict__ D, int64_t ldd,
-                                                          int s, double* __restrict__ V,
-                                                          int64_t ldv, int64_t row0,
-                                                          unsigned long long* bad) {
+__global__ __launch_bounds__(2 * kLeaf) void chol_leaf_kernel(double* __restrict__ D,
+                                                              int64_t ldd, int s,
+                                                              double* __restrict__ V,
+                                                              int64_t ldv, int64_t row0,
+                                                              unsigned long long* bad) {
   __shared__ __attribute__((aligned(16))) double Lc[kLeaf][kLdc];
   __shared__ double rdiag[kLeaf];
   typedef double D2 __attribute__((ext_vector_type(2)));
-  const int i = threadIdx.x;
-  // coalesced load (lane i takes column i of every row), staged in Lc
-  for (int r = 0; r < kLeaf; ++r) {
-    double v = (r == i) ? 1.0 : 0.0;
-    if (r < s && i <= r) v = D[(int64_t)r * ldd + i];
-    Lc[r][i] = v;
-  }
-  __syncthreads();
-  double a[kLeaf];
+  const int tid = threadIdx.x, i = tid % kLeaf;
+  const bool w0 = tid < kLeaf;    // wave 0 factors, wave 1 inverts
+  // coalesced load, all loads of a thread issued before any is used: thread
+  // (wave w, lane i) takes column i of rows w, w + 2, ...
+  {
+    double v[kLeaf / 2];
 #pragma unroll
-  for (int c = 0; c < kLeaf; c += 2) {
-    const D2 v = *reinterpret_cast<const D2*>(&Lc[i][c]);
-    a[c] = v.x;
-    a[c + 1] = v.y;
+    for (int q = 0; q < kLeaf / 2; ++q) {
+      const int r = 2 * q + (w0 ? 0 : 1);
+      v[q] = (r < s && i <= r) ? D[(int64_t)r * ldd + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLeaf / 2; ++q) {
+      const int r = 2 * q + (w0 ? 0 : 1);
+      Lc[r][i] = (r >= s && r == i) ? 1.0 : v[q];
+    }
   }
   __syncthreads();
-  // the loop is kept free of branches (they split it into blocks that the
-  // register allocator handles badly): failures are collected in `first`
+  double a[kLeaf];   // wave 0: row i of the block; wave 1: column i of the inverse
+  if (w0) {
+#pragma unroll
+    for (int c = 0; c < kLeaf; c += 2) {
+      const D2 v = *reinterpret_cast<const D2*>(&Lc[i][c]);
+      a[c] = v.x;
+      a[c + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) a[r] = (r == i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // the loop is kept free of per-lane branches (they split it into blocks that
+  // the register allocator handles badly): failures are collected in `first`.
+  // Column j + 1 is finished and published right after its own update in
+  // step j, so its square root and division can overlap the rest of step j.
   int first = kLeaf;
-#pragma unroll
-  for (int j = 0; j < kLeaf; ++j) {
+  auto publish = [&](int j) {
     double piv = lane_value(a[j], j);
     const bool ok = piv > 0.0;
     first = (!ok && first == kLeaf) ? j : first;
@@ -114,50 +134,68 @@ __global__ __launch_bounds__(kLeaf) void chol_leaf_kernel(double* __restrict__ D
     a[j] = l;
     Lc[j][i] = l;
     rdiag[j] = 1.0 / d;
+  };
+  if (w0) publish(0);
+  // Steps go in groups of kGroup between barriers: wave 0 factors group g
+  // while wave 1 inverts with the columns of group g - 1.
+#pragma unroll
+  for (int g = 0; g <= kLeaf / kGroup; ++g) {
+    if (w0 && g < kLeaf / kGroup) {
+#pragma unroll
+      for (int j = g * kGroup; j < (g + 1) * kGroup && j + 1 < kLeaf; ++j) {
+        const double l = a[j];
+        // l_{j+1,j} straight from lane j + 1: the next pivot's chain
+        // does not wait for LDS
+        a[j + 1] = fma(-l, lane_value(l, j + 1), a[j + 1]);
+        publish(j + 1);
+        // the rest of the row, c >= j + 2, in pairs read kAhead pairs ahead
+        const int q0 = (j + 2) / 2;
+        D2 buf[kLeaf / 2];
+#pragma unroll
+        for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
+          buf[q] = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
+#pragma unroll
+        for (int q = q0; q < kLeaf / 2; ++q) {
+          if (q + kAhead < kLeaf / 2)
+            buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[j][2 * (q + kAhead)]);
+          if (2 * q >= j + 2) a[2 * q] = fma(-l, buf[q].x, a[2 * q]);
+          a[2 * q + 1] = fma(-l, buf[q].y, a[2 * q + 1]);
+        }
+      }
+    }
+    if (!w0 && g >= 1) {
+#pragma unroll
+      for (int jj = (g - 1) * kGroup; jj < g * kGroup; ++jj) {
+        // column jj of L was published before the last barrier
+        a[jj] *= rdiag[jj];
+        const int q0 = (jj + 1) / 2;
+        D2 buf[kLeaf / 2];
+#pragma unroll
+        for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
+          buf[q] = *reinterpret_cast<const D2*>(&Lc[jj][2 * q]);
+#pragma unroll
+        for (int q = q0; q < kLeaf / 2; ++q) {
+          if (q + kAhead < kLeaf / 2)
+            buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[jj][2 * (q + kAhead)]);
+          if (2 * q > jj) a[2 * q] = fma(-buf[q].x, a[jj], a[2 * q]);
+          a[2 * q + 1] = fma(-buf[q].y, a[jj], a[2 * q + 1]);
+        }
+      }
+    }
     __syncthreads();
-    // pairs q = c / 2 from the one holding column j + 1; each read is
-    // issued kAhead pairs before its use
-    const int q0 = (j + 1) / 2;
-    D2 buf[kLeaf / 2];
-#pragma unroll
-    for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
-      buf[q] = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
-#pragma unroll
-    for (int q = q0; q < kLeaf / 2; ++q) {
-      if (q + kAhead < kLeaf / 2) buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[j][2 * (q + kAhead)]);
-      if (2 * q > j) a[2 * q] = fma(-l, buf[q].x, a[2 * q]);
-      a[2 * q + 1] = fma(-l, buf[q].y, a[2 * q + 1]);
-    }
   }
-  if (i == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
-  __syncthreads();
-  // L back to D, rows coalesced: element (r, i) is Lc[i][r]
-  for (int r = 0; r < s; ++r)
+  if (tid == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
+  // L back to D, rows coalesced (element (r, i) is Lc[i][r]), both waves
+  for (int r = (w0 ? 0 : 1); r < s; r += 2)
     if (i <= r) D[(int64_t)r * ldd + i] = Lc[i][r];
-  double x[kLeaf];
-#pragma unroll
-  for (int r = 0; r < kLeaf; ++r) x[r] = (r == i) ? 1.0 : 0.0;
-#pragma unroll
-  for (int j = 0; j < kLeaf; ++j) {
-    x[j] *= rdiag[j];
-    const int q0 = (j + 1) / 2;
-    D2 buf[kLeaf / 2];
-#pragma unroll
-    for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
-      buf[q] = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
-#pragma unroll
-    for (int q = q0; q < kLeaf / 2; ++q) {
-      if (q + kAhead < kLeaf / 2) buf[q + kAhead] = *reinterpret_cast<const D2*>(&Lc[j][2 * (q + kAhead)]);
-      if (2 * q > j) x[2 * q] = fma(-buf[q].x, x[j], x[2 * q]);
-      x[2 * q + 1] = fma(-buf[q].y, x[j], x[2 * q + 1]);
-    }
-  }
+  __syncthreads();
   // column i of the inverse through LDS, then coalesced rows (r >= i)
-  __syncthreads();
+  if (!w0) {
 #pragma unroll
-  for (int r = 0; r < kLeaf; ++r) Lc[r][i] = x[r];
+    for (int r = 0; r < kLeaf; ++r) Lc[r][i] = a[r];
+  }
   __syncthreads();
-  for (int r = 0; r < kLeaf; ++r)
+  for (int r = (w0 ? 0 : 1); r < kLeaf; r += 2)
     if (i <= r) V[(int64_t)r * ldv + i] = Lc[r][i];
 }
 
@@ -233,7 +271,7 @@ trsm_status factor_diag(const Ctx& c, int64_t r0, int64_t s, double* V) {
   const int64_t lda = c.lda, nb = c.nb;
   double* D = c.A + r0 * lda + r0;
   if (s <= kLeaf) {
-    chol_leaf_kernel<<<1, kLeaf, 0, c.s>>>(D, lda, (int)s, V, nb, r0, c.bad);
+    chol_leaf_kernel<<<1, 2 * kLeaf, 0, c.s>>>(D, lda, (int)s, V, nb, r0, c.bad);
     CHOL_HIP(hipGetLastError());
     return TRSM_OK;
   }
