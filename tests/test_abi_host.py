@@ -220,9 +220,10 @@ def test_transposed_plans(T):
 
 
 def test_cholesky_sizes_and_validation_without_gpu(T):
-    # default block: min(512, next power of two >= max(n, 64))
+    # default block: 512 from n = 12288 on, 256 below, at most pow2 >= max(n, 64)
     assert T.trsm_chol_sizes(10)[0] == 64
     assert T.trsm_chol_sizes(100)[0] == 128
+    assert T.trsm_chol_sizes(8192)[0] == 256
     assert T.trsm_chol_sizes(16384)[0] == 512
     nb, lb, wb = T.trsm_chol_sizes(1000, 128)
     m = (1000 + 127) // 128
