@@ -531,7 +531,27 @@ def main():
     tflops = flops_step / (ms_step * 1e-3) / 1e12
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {tflops:.2f} TFLOP/s (n^2 k)")
 
-    # untimed: untouched-step time without event brackets (for reference)
+    # after the timed region: per-step distribution with the inversion and
+    # the sweep bracketed separately (hipEvents on the solve stream)
+    inv_ms, sol_ms, stp_ms = [], [], []
+    for _ in range(max(args.steps, 10)):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        solver.invert(Ld)
+        e[1].record(stream)
+        solver.solve(Ld, Bd, Xd)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        inv_ms.append(e[0].elapsed_time(e[1]))
+        sol_ms.append(e[1].elapsed_time(e[2]))
+        stp_ms.append(e[0].elapsed_time(e[2]))
+    step_stats = {"runs": len(stp_ms), "step_ms_median": round(float(np.median(stp_ms)), 3),
+                  "step_ms_p90": round(float(np.percentile(stp_ms, 90)), 3),
+                  "invert_ms_median": round(float(np.median(inv_ms)), 3),
+                  "solve_ms_median": round(float(np.median(sol_ms)), 3)}
+    log(f"per step: median {step_stats['step_ms_median']} ms (p90 {step_stats['step_ms_p90']}), "
+        f"invert {step_stats['invert_ms_median']} ms, solve {step_stats['solve_ms_median']} ms")
+
     workload = f"trsm_{args.precision}_n{n}_k{k}"
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     peak = PEAK[args.precision]
@@ -624,6 +644,7 @@ def main():
                    "n0_source": "fixed" if args.n0 else ("autotune" if tune else "cost model"),
                    "autotune": tune},
         "roofline": roofline,
+        "step_stats": step_stats,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "serving": serving,
