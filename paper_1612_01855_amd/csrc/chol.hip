@@ -318,14 +318,22 @@ struct Side {
 constexpr int kMaxDevices = 64;
 Side g_side[kMaxDevices];
 
-trsm_status side_for(Side** out) {
+// The device's side stream and events, created on first use (under the
+// device's mutex, which the caller then keeps while it enqueues); they live
+// until the process ends.
+trsm_status side_for(Side** out, std::unique_lock<std::mutex>* lock) {
   int dev = 0;
   CHOL_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return TRSM_EINVAL;
   Side& sd = g_side[dev];
+  *lock = std::unique_lock<std::mutex>(sd.mu);
   if (!sd.s2) {
-    CHOL_HIP(hipStreamCreateWithFlags(&sd.s2, hipStreamNonBlocking));
-    for (auto& e : sd.ev) CHOL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    CHOL_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    for (auto& e : ev) CHOL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) sd.ev[i] = ev[i];
+    sd.s2 = s2;
   }
   *out = &sd;
   return TRSM_OK;
@@ -489,8 +497,8 @@ trsm_status trsm_chol_factor(int64_t n, double* A, int64_t lda, int64_t nb, doub
   // the lookahead pays once there are a few blocks to overlap
   if ((n + z.nb - 1) / z.nb <= 2) return factor_serial(c);
   Side* sd = nullptr;
-  CHOL_TRY(side_for(&sd));
-  std::lock_guard<std::mutex> g(sd->mu);
+  std::unique_lock<std::mutex> lock;
+  CHOL_TRY(side_for(&sd, &lock));
   return factor_lookahead(c, *sd);
 }
 

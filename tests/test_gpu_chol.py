@@ -193,3 +193,43 @@ def test_empty(torch, T):
     Ad = torch.zeros((1, 1), dtype=torch.float64, device="cuda")
     T.trsm_chol_factor(0, Ad.data_ptr(), 1, 0, c.linv_ptr, c.workspace_ptr, 0)
     assert c.check() == (T.OK, -1)
+
+
+def test_concurrent_factorizations_on_two_streams(torch, T):
+    # two host threads, each with its own stream and buffers, share the
+    # library's side stream: both results must equal their lone results
+    import threading
+    n, nb = 1100, 128
+    mats = [gen.spd(n, 40 + t) for t in range(2)]
+    lone = []
+    for A in mats:
+        L, _, _, c = gpu_factor(torch, T, A, nb)
+        assert c.check() == (T.OK, -1)
+        lone.append(L)
+    out = [None, None]
+    errors = []
+
+    def work(t):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                Ad = torch.from_numpy(mats[t]).cuda()
+                c = T.Cholesky(n, nb, device="cuda")
+                for _ in range(3):
+                    Ad.copy_(torch.from_numpy(mats[t]))
+                    T.trsm_chol_factor(n, Ad.data_ptr(), n, nb, c.linv_ptr, c.workspace_ptr,
+                                       s.cuda_stream)
+                s.synchronize()
+                assert c.check() == (T.OK, -1)
+                out[t] = np.tril(Ad.cpu().numpy())
+        except Exception as e:   # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors
+    for t in range(2):
+        assert np.array_equal(out[t], lone[t])
