@@ -183,3 +183,81 @@ def test_cholesky_factors_mixed_with_triangular_ones(torch, T, n0):
             assert np.array_equal(q["Xd"].cpu().numpy(), X)
     finally:
         T.trsm_server_destroy(srv)
+
+
+def test_concurrent_submitters_and_registration(torch, T):
+    """Four host threads submit and poll at once while a fifth registers a new
+    factor; every request's X is bitwise its lone result (computed first,
+    one request at a time) and within 1e-12 of the oracle."""
+    import threading
+    srv = T.trsm_server_create(2 << 30, 16, 128)
+    try:
+        ns = [96, 333, 700]
+        Ls, lids = [], []
+        for i, n in enumerate(ns):
+            L = gen.easy_lower(n, 200 + i)
+            lids.append(T.trsm_server_register_L(srv, torch.from_numpy(L).cuda().data_ptr(), n, n))
+            Ls.append(L)
+        torch.cuda.synchronize()
+        g = gen.rng(9)
+        reqs = []
+        for r in range(24):
+            f = int(g.integers(0, len(ns)))
+            k = int(gen.log_uniform_int(g, 1, 200))
+            B = gen.rhs(ns[f], k, 900 + r)
+            reqs.append(dict(f=f, k=k, B=B, Bd=torch.from_numpy(B).cuda(),
+                             Xd=torch.full((ns[f], k), float("nan"), dtype=torch.float64,
+                                           device="cuda")))
+        torch.cuda.synchronize()
+        lone = []
+        for q in reqs:
+            t = T.trsm_serve_submit(srv, lids[q["f"]], q["Bd"].data_ptr(), q["k"], q["k"],
+                                    q["Xd"].data_ptr(), q["k"])
+            assert wait_all(T, srv, [t])[t][0] == T.REQ_DONE
+            lone.append(q["Xd"].cpu().numpy().copy())
+            q["Xd"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        errors = []
+        extra = {}
+
+        def submitter(part):
+            try:
+                mine = [q for i, q in enumerate(reqs) if i % 4 == part]
+                ts = [T.trsm_serve_submit(srv, lids[q["f"]], q["Bd"].data_ptr(), q["k"], q["k"],
+                                          q["Xd"].data_ptr(), q["k"]) for q in mine]
+                res = wait_all(T, srv, ts)
+                assert all(res[t][0] == T.REQ_DONE for t in ts)
+            except Exception as e:   # reported below
+                errors.append(e)
+
+        def registrar():
+            try:
+                L = gen.easy_lower(512, 777)
+                Ld = torch.from_numpy(L).cuda()
+                extra["lid"] = T.trsm_server_register_L(srv, Ld.data_ptr(), 512, 512)
+                extra["L"] = L
+            except Exception as e:
+                errors.append(e)
+
+        th = [threading.Thread(target=submitter, args=(p,)) for p in range(4)]
+        th.append(threading.Thread(target=registrar))
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert not errors, errors
+        for q, X in zip(reqs, lone):
+            Xc = q["Xd"].cpu().numpy()
+            assert np.array_equal(Xc, X)
+            assert oracle.rel_fro_err(Xc, oracle.trsm(Ls[q["f"]], q["B"])) <= 1e-12
+        # the factor registered during the run serves correctly afterwards
+        B = gen.rhs(512, 17, 5)
+        Bd = torch.from_numpy(B).cuda()
+        Xd = torch.empty_like(Bd)
+        t = T.trsm_serve_submit(srv, extra["lid"], Bd.data_ptr(), 17, 17, Xd.data_ptr(), 17)
+        assert wait_all(T, srv, [t])[t][0] == T.REQ_DONE
+        assert oracle.rel_fro_err(Xd.cpu().numpy(), oracle.trsm(extra["L"], B)) <= 1e-12
+        stats = T.trsm_server_stats(srv)
+        assert stats.failed == 0 and stats.completed == 2 * len(reqs) + 1
+    finally:
+        T.trsm_server_destroy(srv)
