@@ -26,6 +26,8 @@ What it computes (all in IEEE binary64 unless stated):
 * ``chol(A)`` -- the Cholesky factor A = L L^T of a symmetric positive
   definite A by its column-by-column definition (the factorization whose
   panel step is a triangular solve, named in the abstract and Sec. I).
+* ``lu_nopiv(A)`` -- LU factors A = L U without row exchanges by Doolittle's
+  definition (the other factorization named there, in its no-pivoting form).
 * ``oracle.exact`` -- exact rational arithmetic (Gauss-Jordan on Q) for
   brute-force pins at tiny n.
 
@@ -87,6 +89,8 @@ def _load():
         lib.oracle_fro_dense.restype = ctypes.c_double
         lib.oracle_chol_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
         lib.oracle_chol_f64.restype = ci
+        lib.oracle_lu_nopiv_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
+        lib.oracle_lu_nopiv_f64.restype = ci
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ci
         _lib = lib
@@ -219,6 +223,27 @@ def chol(A, nthreads: int = 0):
     if rc != 0:
         raise ValueError("oracle_chol_f64 rejected the sizes")
     return L, int(fail.value)
+
+
+def lu_nopiv(A, nthreads: int = 0):
+    """LU factors without pivoting, A = L U (Doolittle): returns (L, U, fail)
+    with L unit lower triangular, U upper triangular, and fail = -1, or the
+    first step whose pivot is zero or not finite (the factors are then
+    unspecified from there on)."""
+    lib = _load()
+    A = _rows(A)
+    n = A.shape[0]
+    if A.shape[1] < n:
+        raise ValueError("A must be n x n")
+    LU = np.empty((n, n), dtype=np.float64)
+    fail = ctypes.c_int64(-1)
+    rc = lib.oracle_lu_nopiv_f64(n, A.ctypes.data, _ld(A), LU.ctypes.data, max(n, 1),
+                                 int(nthreads), ctypes.byref(fail))
+    if rc != 0:
+        raise ValueError("oracle_lu_nopiv_f64 rejected the sizes")
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    return L, U, int(fail.value)
 
 
 def rel_fro_err(X, Xref) -> float:

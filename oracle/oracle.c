@@ -307,6 +307,76 @@ int oracle_chol_f64(int64_t n, const double* A, int64_t lda,
   return 0;
 }
 
+/* LU factors without pivoting, A = L U, L unit lower triangular and U upper
+ * triangular: the other factorization the abstract and Sec. I name as built
+ * on TRSM, in its no-exchange form (the matrices it is meant for need no row
+ * exchanges, e.g. diagonally dominant ones).  Doolittle's definition written
+ * out, step j ascending:
+ *
+ *     u[j][c] = a[j][c] - sum_{p<j} l[j][p] * u[p][c],          c >= j
+ *     l[i][j] = ( a[i][j] - sum_{p<j} l[i][p] * u[p][j] ) / u[j][j],   i > j
+ *
+ * each sum taken with p ascending, every product rounded before it is
+ * subtracted, a true division.  A is n x n row-major (lda); LU receives L
+ * strictly below the diagonal (its unit diagonal is not stored) and U on and
+ * above it, the compact form.  LU may be A itself (ldu == lda).  Threads
+ * split the rows of each column of L and the columns of each row of U.
+ *
+ * Returns 0, or -1 on bad sizes.  *fail receives -1, or the first j whose
+ * pivot u[j][j] is zero or not finite; LU is then unspecified from row and
+ * column j on. */
+int oracle_lu_nopiv_f64(int64_t n, const double* A, int64_t lda,
+                        double* LU, int64_t ldu, int nthreads, int64_t* fail) {
+  if (fail != NULL) *fail = -1;
+  if (n < 0) return -1;
+  if (n == 0) return 0;
+  if (lda < n || ldu < n) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    double* ui = LU + i * ldu;
+    const double* ai = A + i * lda;
+    if (ui != ai)
+      for (int64_t j = 0; j < n; ++j) ui[j] = ai[j];
+  }
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#endif
+  for (int64_t j = 0; j < n; ++j) {
+    double* uj = LU + j * ldu;
+    /* row j of U */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (n - j > 256)
+#endif
+    for (int64_t c = j; c < n; ++c) {
+      double acc = uj[c];
+      for (int64_t p = 0; p < j; ++p) {
+        double term = uj[p] * LU[p * ldu + c];
+        acc = acc - term;
+      }
+      uj[c] = acc;
+    }
+    const double ujj = uj[j];
+    if (!(ujj != 0.0) || !isfinite(ujj)) {
+      if (fail != NULL) *fail = j;
+      return 0;
+    }
+    /* column j of L */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (n - j > 256)
+#endif
+    for (int64_t i = j + 1; i < n; ++i) {
+      double* li = LU + i * ldu;
+      double acc = li[j];
+      for (int64_t p = 0; p < j; ++p) {
+        double term = li[p] * LU[p * ldu + j];
+        acc = acc - term;
+      }
+      li[j] = acc / ujj;
+    }
+  }
+  (void)nthreads;
+  return 0;
+}
+
 /* Number of threads the OpenMP runtime would use by default. */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -17,6 +17,8 @@ its problem statement, an n x n lower-triangular L and a dense n x k B):
   hence cond_2(L) ~ 1e6.
 * ``spd`` / ``spd_on`` -- the symmetric positive definite A = G G^T / m + I
   (or + eps I) behind the Cholesky factors, the input of the factorization.
+* ``diag_dominant`` -- nonsymmetric, strictly column diagonally dominant
+  matrices: the input of the LU factorization without row exchanges.
 * ``rhs``         -- B ~ N(0,1).
 * closed-form matrices used as pins (identity, diagonal, bidiagonal,
   all-ones lower triangle, random integer unit-lower).
@@ -182,6 +184,38 @@ def int_lower_positive(n: int, seed: int, lo: int = -2, hi: int = 2,
     L = np.tril(g.integers(lo, hi + 1, size=(n, n)), -1).astype(np.float64)
     L[np.arange(n), np.arange(n)] = g.integers(1, dmax + 1, size=n)
     return L
+
+
+def diag_dominant(n: int, seed: int, margin: float = 1.0) -> np.ndarray:
+    """Nonsymmetric A with entries ~ U[-1, 1] off the diagonal and a_jj =
+    sign * (margin + sum_{i != j} |a_ij|) (random sign): strictly column
+    diagonally dominant, so elimination without row exchanges is stable and
+    partial pivoting would not exchange any row."""
+    g = rng(seed)
+    A = g.uniform(-1.0, 1.0, size=(n, n))
+    A[np.arange(n), np.arange(n)] = 0.0
+    col = np.abs(A).sum(axis=0)
+    sign = np.where(g.uniform(size=n) < 0.5, -1.0, 1.0)
+    A[np.arange(n), np.arange(n)] = sign * (margin + col)
+    return np.ascontiguousarray(A)
+
+
+def int_unit_lower_small(n: int, seed: int, lo: int = -2, hi: int = 2) -> np.ndarray:
+    """Unit lower-triangular integer matrix, strict lower entries in {lo..hi}."""
+    g = rng(seed)
+    L = np.tril(g.integers(lo, hi + 1, size=(n, n)), -1).astype(np.float64)
+    L[np.arange(n), np.arange(n)] = 1.0
+    return L
+
+
+def int_upper_pow2(n: int, seed: int, lo: int = -2, hi: int = 2) -> np.ndarray:
+    """Upper-triangular integer matrix with diagonal entries +-1, +-2 or +-4 and
+    strict upper entries in {lo..hi}: A = L U for an integer unit-lower L is an
+    integer matrix whose no-pivoting LU divisions are exact."""
+    g = rng(seed)
+    U = np.triu(g.integers(lo, hi + 1, size=(n, n)), 1).astype(np.float64)
+    U[np.arange(n), np.arange(n)] = g.choice([-4.0, -2.0, -1.0, 1.0, 2.0, 4.0], size=n)
+    return U
 
 
 # ---- closed-form matrices (pins) -------------------------------------------
