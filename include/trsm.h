@@ -408,6 +408,39 @@ trsm_status trsm_chol_factor(int64_t n, double* A, int64_t lda, int64_t nb, doub
 trsm_status trsm_chol_check(const void* workspace, trsm_status* status, int64_t* index);
 
 /*
+ * Blocked LU factorization WITHOUT row exchanges, A = L U (binary64; L unit
+ * lower, U upper), for matrices that need none (e.g. diagonally dominant
+ * ones, or after a randomizing transform); partial pivoting is not provided.
+ * Its two panel steps are the triangular solve of Alg. It-Inv-TRSM with the
+ * whole diagonal block inverted (the abstract and Sec. I name LU as built on
+ * TRSM): U(S_j, T_j) = Linv_jj A(S_j, T_j) and L(T_j, S_j) = A(T_j, S_j)
+ * Uinv_jj, then A(T_j, T_j) -= L(T_j, S_j) U(S_j, T_j).  The diagonal blocks
+ * are factored recursively (64 x 64 leaves in LDS) and both inverses built
+ * by Alg. RecTriInv's combine along the way; the same two-stream lookahead as
+ * trsm_chol_factor.
+ *
+ * trsm_lu_sizes(n, nb, &nb_used, &inv_bytes, &workspace_bytes): as
+ *  trsm_chol_sizes; inv_bytes is the size of EACH of the Linv and Uinv
+ *  buffers.
+ * trsm_lu_factor(n, A, lda, nb, Linv, Uinv, workspace, stream): A (device,
+ *  row-major, lda >= n) is overwritten with L strictly below the diagonal (its
+ *  unit diagonal is not stored) and U on and above it.  Linv receives the
+ *  unit lower inverses of L's diagonal blocks (diagonal 1 stored, zeros
+ *  above: a TRSM_F64 plan with n0 = nb_used solves L Y = B with A as its L
+ *  and these blocks, since its sweep reads only the strictly lower part of A
+ *  outside the blocks), Uinv the upper inverses of U's (zeros below); ragged
+ *  last blocks padded with the identity.  Other arguments and behaviour as
+ *  trsm_chol_factor.
+ * trsm_lu_check(workspace, &status, &index): TRSM_OK and -1, or
+ *  TRSM_ESINGULAR and the first row whose pivot was zero or not finite.
+ */
+trsm_status trsm_lu_sizes(int64_t n, int64_t nb, int64_t* nb_used, size_t* inv_bytes,
+                          size_t* workspace_bytes);
+trsm_status trsm_lu_factor(int64_t n, double* A, int64_t lda, int64_t nb, double* Linv,
+                           double* Uinv, void* workspace, void* stream);
+trsm_status trsm_lu_check(const void* workspace, trsm_status* status, int64_t* index);
+
+/*
  * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes
  * every matrix-core product launched by trsm_invert_diag and trsm_solve with
  * this plan record a pair of hipEvents around itself on the call's stream

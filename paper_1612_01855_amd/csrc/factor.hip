@@ -1,6 +1,7 @@
-// Blocked Cholesky factorization A = L L^T (binary64) whose panel step is the
-// triangular solve of Alg. It-Inv-TRSM with whole inverted diagonal blocks,
-// and the C ABI trsm_chol_* (see include/trsm.h).
+// Blocked factorizations whose panel steps are the triangular solve of Alg.
+// It-Inv-TRSM with whole inverted diagonal blocks: Cholesky A = L L^T (C ABI
+// trsm_chol_*) and LU without row exchanges A = L U (trsm_lu_*), both binary64
+// (see include/trsm.h).
 //
 // The abstract and Sec. I name Cholesky as a factorization whose main
 // subroutine is TRSM.  Right-looking, block size nb:
@@ -213,12 +214,87 @@ __global__ void chol_init_kernel(double* __restrict__ V, int64_t n, int64_t nb, 
   }
 }
 
+// LU leaf: the s x s (s <= 64) diagonal block D is factored without row
+// exchanges in LDS by 256 threads, right-looking, step j:
+//   u_jc = d_jc (c >= j, already updated),  l_ij = d_ij / u_jj (i > j),
+//   d_ic -= l_ij u_jc (i, c > j);
+// then threads 0..63 form column t of L's unit lower inverse and threads
+// 64..127 column t of U's inverse, by substitution on the identity:
+//   x_rt = -sum_{p<r} l_rp x_pt (r > t, x_tt = 1),
+//   y_rt = -(sum_{p>r} u_rp y_pt) / u_rr (r < t, y_tt = 1 / u_tt),
+// every lane walking the same (r, p) so that l_rp and u_rp are LDS
+// broadcasts.  L (strictly lower) and U go back to D, the inverses to VL (unit
+// lower, diagonal stored) and VU (upper), ld ldv, nothing written on their
+// other side.  A zero or non-finite pivot records its global row in *bad (the
+// smallest one wins) and is replaced by 1 in the divisions.
+__global__ __launch_bounds__(256) void lu_leaf_kernel(double* __restrict__ D, int64_t ldd, int s,
+                                                      double* __restrict__ VL,
+                                                      double* __restrict__ VU, int64_t ldv,
+                                                      int64_t row0, unsigned long long* bad) {
+  __shared__ double S[kLeaf][kLeaf + 1];
+  __shared__ double XL[kLeaf][kLeaf + 1];
+  __shared__ double XU[kLeaf][kLeaf + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < kLeaf * kLeaf; e += 256) {
+    const int i = e / kLeaf, j = e % kLeaf;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < s && j < s) v = D[(int64_t)i * ldd + j];
+    S[i][j] = v;
+  }
+  __syncthreads();
+  const int row = t % kLeaf, cg = t / kLeaf;
+  int first = kLeaf;
+  for (int j = 0; j < s; ++j) {
+    double piv = S[j][j];
+    const bool ok = (piv != 0.0) && isfinite(piv);
+    first = (!ok && first == kLeaf) ? j : first;
+    piv = ok ? piv : 1.0;
+    if (t > j && t < s) S[t][j] = S[t][j] / piv;
+    __syncthreads();
+    if (row > j && row < s) {
+      const double lij = S[row][j];
+      for (int c = j + 1 + cg; c < s; c += 4) S[row][c] -= lij * S[j][c];
+    }
+    __syncthreads();
+  }
+  if (t == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
+  if (t < kLeaf) {
+    for (int r = 0; r < kLeaf; ++r) XL[r][t] = (r == t) ? 1.0 : 0.0;
+    for (int r = 1; r < kLeaf; ++r) {
+      if (t < r) {
+        double acc = 0.0;
+        for (int p = 0; p < r; ++p) acc += S[r][p] * XL[p][t];
+        XL[r][t] = -acc;
+      }
+    }
+  } else if (t < 2 * kLeaf) {
+    const int tc = t - kLeaf;
+    for (int r = 0; r < kLeaf; ++r) XU[r][tc] = (r == tc) ? 1.0 / S[tc][tc] : 0.0;
+    for (int r = kLeaf - 2; r >= 0; --r) {
+      if (tc > r) {
+        double acc = 0.0;
+        for (int p = r + 1; p < kLeaf; ++p) acc += S[r][p] * XU[p][tc];
+        XU[r][tc] = -acc / S[r][r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < kLeaf * kLeaf; e += 256) {
+    const int i = e / kLeaf, j = e % kLeaf;
+    if (i < s && j < s) D[(int64_t)i * ldd + j] = S[i][j];
+    if (j <= i) VL[(int64_t)i * ldv + j] = XL[i][j];
+    if (j >= i) VU[(int64_t)i * ldv + j] = XU[i][j];
+  }
+}
+
 struct Ctx {
   double* A;
   int64_t lda, n, nb;
-  double* V;      // m inverted diagonal blocks, nb x nb each
-  double* W;      // nb x nb: the diagonal block's panel and combine
-  double* W2[2];  // (n - nb) x nb each: the outer panel L(T_j, S_j), by parity of j
+  double* V = nullptr;      // m inverted diagonal blocks, nb x nb each (LU: of L)
+  double* VU = nullptr;     // LU: m inverted diagonal blocks of U
+  double* W = nullptr;      // nb x nb: the diagonal block's panel and combine
+  double* W2[2] = {};       // (n - nb) x nb each: the outer panel L(T_j, S_j), by parity of j
+  double* WU[2] = {};       // LU: nb x (n - nb) each: the outer panel U(S_j, T_j)
   void* split;    // split-K scratch
   size_t split_bytes;
   unsigned long long* bad;
@@ -423,12 +499,154 @@ trsm_status factor_lookahead(const Ctx& c, Side& sd) {
   return TRSM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// LU without row exchanges.  Diagonal block of s rows at global row r0, its
+// inverses at VL / VU (ld nb): halves h and s - h,
+//   factor D11 -> L11, U11, Linv11, Uinv11;
+//   L21 = D21 Uinv11;  U12 = Linv11 D12;  D22 -= L21 U12;
+//   factor D22 -> L22, U22, Linv22, Uinv22;
+//   Linv21 = -(Linv22 L21) Linv11;  Uinv12 = -(Uinv11 U12) Uinv22,
+// the last two being Alg. RecTriInv's combine for the lower and the upper
+// factor.
+trsm_status lu_factor_diag(const Ctx& c, int64_t r0, int64_t s, double* VL, double* VU) {
+  const int64_t lda = c.lda, nb = c.nb;
+  double* D = c.A + r0 * lda + r0;
+  if (s <= kLeaf) {
+    lu_leaf_kernel<<<1, 256, 0, c.s>>>(D, lda, (int)s, VL, VU, nb, r0, c.bad);
+    CHOL_HIP(hipGetLastError());
+    return TRSM_OK;
+  }
+  const int64_t h = kLeaf * ((s + 2 * kLeaf - 1) / (2 * kLeaf));
+  const int64_t t = s - h;
+  double* D12 = D + h;
+  double* D21 = D + h * lda;
+  double* D22 = D21 + h;
+  CHOL_TRY(lu_factor_diag(c, r0, h, VL, VU));
+  // L21 = D21 Uinv11 and U12 = Linv11 D12.  With h <= 64 each product has
+  // one tile along the dimension it overwrites (columns of L21, rows of U12),
+  // so every workgroup reads its part of the operand in full before writing
+  // it and the product runs in place; otherwise it goes through W.
+  if (h <= kLeaf) {
+    CHOL_HIP(prod<false>(c, D21, lda, VU, nb, D21, lda, t, h, h, 1.0, false, 0u, false));
+    CHOL_HIP(prod<false>(c, VL, nb, D12, lda, D12, lda, h, t, h, 1.0, false,
+                         G_A_LOWER | G_A_ZERO_UPPER, false));
+  } else {
+    CHOL_HIP(prod<false>(c, D21, lda, VU, nb, c.W, nb, t, h, h, 1.0, false, 0u, false));
+    CHOL_HIP(launch_copy2d<double, double>(c.W, nb, D21, lda, t, h, 1.0, c.s));
+    CHOL_HIP(prod<false>(c, VL, nb, D12, lda, c.W, nb, h, t, h, 1.0, false,
+                         G_A_LOWER | G_A_ZERO_UPPER, false));
+    CHOL_HIP(launch_copy2d<double, double>(c.W, nb, D12, lda, h, t, 1.0, c.s));
+  }
+  // D22 -= L21 U12
+  CHOL_HIP(prod<false>(c, D21, lda, D12, lda, D22, lda, t, t, h, -1.0, true, 0u, false));
+  CHOL_TRY(lu_factor_diag(c, r0 + h, t, VL + h * nb + h, VU + h * nb + h));
+  // Linv21 = -(Linv22 L21) Linv11
+  CHOL_HIP(prod<false>(c, VL + h * nb + h, nb, D21, lda, c.W, nb, t, h, t, 1.0, false,
+                       G_A_LOWER | G_A_ZERO_UPPER, false));
+  CHOL_HIP(prod<false>(c, c.W, nb, VL, nb, VL + h * nb, nb, t, h, h, -1.0, false, G_B_LOWER,
+                       false));
+  // Uinv12 = -(Uinv11 U12) Uinv22
+  CHOL_HIP(prod<false>(c, VU, nb, D12, lda, c.W, nb, h, t, h, 1.0, false, G_A_UPPER, false));
+  CHOL_HIP(prod<false>(c, c.W, nb, VU + h * nb + h, nb, VU + h, nb, h, t, t, -1.0, false, 0u,
+                       false));
+  return TRSM_OK;
+}
+
+trsm_status lu_init(const Ctx& c, int64_t m) {
+  CHOL_TRY(init(c, m));
+  Ctx cu = c;
+  cu.V = c.VU;
+  return init(cu, m);
+}
+
+// One stream: diagonal block, both panels, trailing update, in order.
+trsm_status lu_factor_serial(const Ctx& c) {
+  const int64_t n = c.n, nb = c.nb, m = (n + nb - 1) / nb, lda = c.lda;
+  CHOL_TRY(lu_init(c, m));
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t r0 = j * nb, s = std::min(nb, n - r0), t = n - r0 - s;
+    double* VLj = c.V + j * nb * nb;
+    double* VUj = c.VU + j * nb * nb;
+    CHOL_TRY(lu_factor_diag(c, r0, s, VLj, VUj));
+    if (t <= 0) break;
+    double* A12 = c.A + r0 * lda + r0 + s;
+    double* A21 = c.A + (r0 + s) * lda + r0;
+    double* A22 = A21 + s;
+    const int64_t ldu = n - nb;
+    // L(T_j, S_j) = A(T_j, S_j) Uinv_jj;  U(S_j, T_j) = Linv_jj A(S_j, T_j)
+    CHOL_HIP(prod<false>(c, A21, lda, VUj, nb, c.W2[0], nb, t, s, s, 1.0, false, 0u));
+    CHOL_HIP(launch_copy2d<double, double>(c.W2[0], nb, A21, lda, t, s, 1.0, c.s));
+    CHOL_HIP(prod<false>(c, VLj, nb, A12, lda, c.WU[0], ldu, s, t, s, 1.0, false,
+                         G_A_LOWER | G_A_ZERO_UPPER));
+    CHOL_HIP(launch_copy2d<double, double>(c.WU[0], ldu, A12, lda, s, t, 1.0, c.s));
+    // A(T_j, T_j) -= L(T_j, S_j) U(S_j, T_j)
+    CHOL_HIP(prod<false>(c, c.W2[0], nb, c.WU[0], ldu, A22, lda, t, t, s, -1.0, true, 0u));
+  }
+  return TRSM_OK;
+}
+
+// Lookahead over two streams, as for Cholesky: update j is split into the
+// next diagonal block (on the caller's stream) and the rest, the rows below
+// it and the columns right of it (on the side stream), which overlaps the
+// factorization of diagonal block j+1; panels j+1 wait for it.
+trsm_status lu_factor_lookahead(const Ctx& c, Side& sd) {
+  const int64_t n = c.n, nb = c.nb, m = (n + nb - 1) / nb, lda = c.lda;
+  const int64_t ldu = n - nb;
+  hipStream_t s2 = sd.s2;
+  Ctx c2 = c;
+  c2.s = s2;
+  c2.split = nullptr;
+  c2.split_bytes = 0;
+  CHOL_TRY(lu_init(c, m));
+  CHOL_HIP(hipEventRecord(sd.ev[0], c.s));
+  CHOL_HIP(hipStreamWaitEvent(s2, sd.ev[0], 0));
+  bool pending = false;
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t r0 = j * nb, s = std::min(nb, n - r0), t = n - r0 - s;
+    double* VLj = c.V + j * nb * nb;
+    double* VUj = c.VU + j * nb * nb;
+    CHOL_TRY(lu_factor_diag(c, r0, s, VLj, VUj));
+    if (t <= 0) break;
+    double* PL = c.W2[j & 1];
+    double* PU = c.WU[j & 1];
+    double* A12 = c.A + r0 * lda + r0 + s;
+    double* A21 = c.A + (r0 + s) * lda + r0;
+    double* A22 = A21 + s;
+    if (pending) CHOL_HIP(hipStreamWaitEvent(c.s, sd.ev[2], 0));
+    CHOL_HIP(prod<false>(c, A21, lda, VUj, nb, PL, nb, t, s, s, 1.0, false, 0u));
+    CHOL_HIP(launch_copy2d<double, double>(PL, nb, A21, lda, t, s, 1.0, c.s));
+    CHOL_HIP(prod<false>(c, VLj, nb, A12, lda, PU, ldu, s, t, s, 1.0, false,
+                         G_A_LOWER | G_A_ZERO_UPPER));
+    CHOL_HIP(launch_copy2d<double, double>(PU, ldu, A12, lda, s, t, 1.0, c.s));
+    const int64_t s1 = std::min(nb, t);
+    // the next diagonal block on the chain
+    CHOL_HIP(prod<false>(c, PL, nb, PU, ldu, A22, lda, s1, s1, s, -1.0, true, 0u));
+    if (t > s1) {
+      CHOL_HIP(hipEventRecord(sd.ev[1], c.s));
+      CHOL_HIP(hipStreamWaitEvent(s2, sd.ev[1], 0));
+      // rows of S_{j+1} right of its diagonal block, then all rows below it
+      CHOL_HIP(prod<false>(c2, PL, nb, PU + s1, ldu, A22 + s1, lda, s1, t - s1, s, -1.0, true,
+                           0u));
+      CHOL_HIP(prod<false>(c2, PL + s1 * nb, nb, PU, ldu, A22 + s1 * lda, lda, t - s1, t, s,
+                           -1.0, true, 0u));
+      CHOL_HIP(hipEventRecord(sd.ev[2], s2));
+      pending = true;
+    } else {
+      pending = false;
+    }
+  }
+  CHOL_HIP(hipEventRecord(sd.ev[2], s2));
+  CHOL_HIP(hipStreamWaitEvent(c.s, sd.ev[2], 0));
+  return TRSM_OK;
+}
+
 struct Sizes {
   int64_t nb;
   size_t linv, off_w, off_w2, w2_bytes, off_split, ws;
+  size_t off_wu = 0;   // LU only: two nb x (n - nb) panels of U after the split scratch
 };
 
-trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z) {
+trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z, bool lu = false) {
   if (n < 0 || nb < 0) return TRSM_EINVAL;
   // measured: 256-row blocks are faster up to n = 8192, 512-row ones at 16384
   if (nb == 0)
@@ -447,6 +665,10 @@ trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z) {
   off += 2 * al((size_t)std::max<int64_t>(n - nb, 1) * nb * 8);
   z->off_split = off;
   off += kCholSplitBytes;
+  if (lu) {
+    z->off_wu = off;
+    off += 2 * z->w2_bytes;
+  }
   z->ws = off;
   return TRSM_OK;
 }
@@ -517,4 +739,56 @@ trsm_status trsm_chol_check(const void* workspace, trsm_status* status, int64_t*
   return TRSM_OK;
 }
 
+trsm_status trsm_lu_sizes(int64_t n, int64_t nb, int64_t* nb_used, size_t* inv_bytes,
+                          size_t* workspace_bytes) {
+  Sizes z;
+  CHOL_TRY(sizes_for(n, nb, &z, true));
+  if (nb_used) *nb_used = z.nb;
+  if (inv_bytes) *inv_bytes = z.linv;
+  if (workspace_bytes) *workspace_bytes = z.ws;
+  return TRSM_OK;
+}
+
+trsm_status trsm_lu_factor(int64_t n, double* A, int64_t lda, int64_t nb, double* Linv,
+                           double* Uinv, void* workspace, void* stream) {
+  Sizes z;
+  CHOL_TRY(sizes_for(n, nb, &z, true));
+  if (!workspace || (n > 0 && (!A || !Linv || !Uinv)) || lda < std::max<int64_t>(n, 1))
+    return TRSM_EINVAL;
+  if (((uintptr_t)workspace & (kAl - 1)) || ((uintptr_t)Linv & 15) || ((uintptr_t)Uinv & 15))
+    return TRSM_EINVAL;
+  Ctx c;
+  c.A = A;
+  c.lda = lda;
+  c.n = n;
+  c.nb = z.nb;
+  c.V = Linv;
+  c.VU = Uinv;
+  char* w = static_cast<char*>(workspace);
+  c.bad = reinterpret_cast<unsigned long long*>(w);
+  c.W = reinterpret_cast<double*>(w + z.off_w);
+  c.W2[0] = reinterpret_cast<double*>(w + z.off_w2);
+  c.W2[1] = reinterpret_cast<double*>(w + z.off_w2 + z.w2_bytes);
+  c.WU[0] = reinterpret_cast<double*>(w + z.off_wu);
+  c.WU[1] = reinterpret_cast<double*>(w + z.off_wu + z.w2_bytes);
+  c.split = w + z.off_split;
+  c.split_bytes = kCholSplitBytes;
+  c.s = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    chol_init_kernel<<<1, 64, 0, c.s>>>(nullptr, 0, z.nb, 0, c.bad);
+    CHOL_HIP(hipGetLastError());
+    return TRSM_OK;
+  }
+  if ((n + z.nb - 1) / z.nb <= 2) return lu_factor_serial(c);
+  Side* sd = nullptr;
+  std::unique_lock<std::mutex> lock;
+  CHOL_TRY(side_for(&sd, &lock));
+  return lu_factor_lookahead(c, *sd);
+}
+
+trsm_status trsm_lu_check(const void* workspace, trsm_status* status, int64_t* index) {
+  return trsm_chol_check(workspace, status, index);
+}
+
 }  // extern "C"
+

@@ -82,7 +82,8 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
            "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy",
-           "trsm_chol_sizes", "trsm_chol_factor", "trsm_chol_check"]
+           "trsm_chol_sizes", "trsm_chol_factor", "trsm_chol_check",
+           "trsm_lu_sizes", "trsm_lu_factor", "trsm_lu_check"]
 
 
 class TrsmError(RuntimeError):
@@ -166,6 +167,13 @@ def _load():
     lib.trsm_chol_factor.restype = i32
     lib.trsm_chol_check.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     lib.trsm_chol_check.restype = i32
+    lib.trsm_lu_sizes.argtypes = [i64, i64, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t),
+                                  ctypes.POINTER(ctypes.c_size_t)]
+    lib.trsm_lu_sizes.restype = i32
+    lib.trsm_lu_factor.argtypes = [i64, vp, i64, i64, vp, vp, vp, vp]
+    lib.trsm_lu_factor.restype = i32
+    lib.trsm_lu_check.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.trsm_lu_check.restype = i32
     return lib
 
 
@@ -360,6 +368,27 @@ def trsm_chol_check(workspace: int):
     return st.value, idx.value
 
 
+def trsm_lu_sizes(n: int, nb: int = 0):
+    """(nb_used, inv_bytes per inverse buffer, workspace_bytes) of an LU
+    factorization without row exchanges."""
+    nbu, lb, wb = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.trsm_lu_sizes(n, nb, ctypes.byref(nbu), ctypes.byref(lb), ctypes.byref(wb)),
+           "trsm_lu_sizes")
+    return nbu.value, lb.value, wb.value
+
+
+def trsm_lu_factor(n: int, A: int, lda: int, nb: int, Linv: int, Uinv: int, workspace: int,
+                   stream: int = 0) -> None:
+    _check(_lib.trsm_lu_factor(n, A, lda, nb, Linv, Uinv, workspace, stream), "trsm_lu_factor")
+
+
+def trsm_lu_check(workspace: int):
+    """(status, index) of the last LU factorization on `workspace` (blocking)."""
+    st, idx = ctypes.c_int(), ctypes.c_int64()
+    _check(_lib.trsm_lu_check(workspace, ctypes.byref(st), ctypes.byref(idx)), "trsm_lu_check")
+    return st.value, idx.value
+
+
 # ---- torch-tensor convenience (memory ownership only) ------------------------
 
 def _stream_handle(torch, device) -> int:
@@ -485,6 +514,76 @@ def cholesky(A, nb: int = 0):
     if st != OK:
         raise TrsmError(st, f"cholesky (row {idx})")
     return L.tril_()
+
+
+class LU:
+    """Owns the Linv, Uinv and workspace buffers of an LU factorization
+    without row exchanges of one size (torch uint8 tensors, aligned views)."""
+
+    def __init__(self, n: int, nb: int = 0, device: str = "cuda"):
+        import torch
+        self.n = n
+        self.nb, lb, wb = trsm_lu_sizes(n, nb)
+        self._linv = torch.empty(max(lb, 1) + 256, dtype=torch.uint8, device=device)
+        self._uinv = torch.empty(max(lb, 1) + 256, dtype=torch.uint8, device=device)
+        self._ws = torch.empty(max(wb, 1) + 256, dtype=torch.uint8, device=device)
+        self.inv_bytes = lb
+
+    @staticmethod
+    def _aligned(buf) -> int:
+        return (buf.data_ptr() + 255) // 256 * 256
+
+    @property
+    def linv_ptr(self) -> int:
+        return self._aligned(self._linv)
+
+    @property
+    def uinv_ptr(self) -> int:
+        return self._aligned(self._uinv)
+
+    @property
+    def workspace_ptr(self) -> int:
+        return self._aligned(self._ws)
+
+    def factor(self, A) -> None:
+        """In place: A becomes L (strictly lower, unit diagonal implied) and U."""
+        import torch
+        if A.dtype != torch.float64 or A.shape[0] != self.n or A.shape[1] < self.n:
+            raise ValueError("A must be an n x n float64 tensor")
+        trsm_lu_factor(self.n, A.data_ptr(), _ld(A), self.nb, self.linv_ptr, self.uinv_ptr,
+                       self.workspace_ptr, _stream_handle(torch, A.device))
+
+    def _blocks(self, buf):
+        import torch
+        m = (self.n + self.nb - 1) // self.nb
+        off = self._aligned(buf) - buf.data_ptr()
+        return buf[off:off + m * self.nb * self.nb * 8].view(torch.float64).view(
+            m, self.nb, self.nb)
+
+    def linv_blocks(self):
+        return self._blocks(self._linv)
+
+    def uinv_blocks(self):
+        return self._blocks(self._uinv)
+
+    def check(self):
+        return trsm_lu_check(self.workspace_ptr)
+
+
+def lu_nopiv(A, nb: int = 0):
+    """(L, U) with A = L U, no row exchanges, on the GPU (A float64).  Raises
+    TrsmError(ESINGULAR) at a zero or non-finite pivot."""
+    import torch
+    n = A.shape[0]
+    F = A.clone()
+    f = LU(n, nb, device=A.device)
+    f.factor(F)
+    st, idx = f.check()
+    if st != OK:
+        raise TrsmError(st, f"lu_nopiv (row {idx})")
+    L = torch.tril(F, -1)
+    L.diagonal().fill_(1.0)
+    return L, torch.triu(F)
 
 
 def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None):

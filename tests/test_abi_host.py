@@ -254,3 +254,22 @@ def test_cholesky_sizes_and_validation_without_gpu(T):
     assert lib.trsm_chol_factor(64, fake, 64, 0, fake + 8, fake, None) == T.EINVAL
     assert lib.trsm_chol_factor(64, fake, 64, 48, fake, fake, None) == T.EINVAL
     assert lib.trsm_chol_check(None, None, None) == T.EINVAL
+
+
+def test_lu_sizes_and_validation_without_gpu(T):
+    nb, lb, wb = T.trsm_lu_sizes(1000, 128)
+    cb = T.trsm_chol_sizes(1000, 128)
+    assert nb == 128 and lb == cb[1]
+    # the Cholesky workspace plus two nb x (n - nb) panels of U
+    assert wb >= cb[2] + 2 * (1000 - 128) * 128 * 8
+    for bad_nb in (32, 96, 8192):
+        with pytest.raises(T.TrsmError):
+            T.trsm_lu_sizes(100, bad_nb)
+    lib = T._lib
+    fake = 1 << 20
+    assert lib.trsm_lu_factor(64, None, 64, 0, fake, fake, fake, None) == T.EINVAL
+    assert lib.trsm_lu_factor(64, fake, 64, 0, None, fake, fake, None) == T.EINVAL
+    assert lib.trsm_lu_factor(64, fake, 64, 0, fake, None, fake, None) == T.EINVAL
+    assert lib.trsm_lu_factor(64, fake, 63, 0, fake, fake, fake, None) == T.EINVAL
+    assert lib.trsm_lu_factor(64, fake, 64, 0, fake, fake + 8, fake, None) == T.EINVAL
+    assert lib.trsm_lu_factor(64, fake, 64, 0, fake, fake, fake + 8, None) == T.EINVAL

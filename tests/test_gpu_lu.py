@@ -1,0 +1,189 @@
+"""GPU parity of the blocked LU factorization without row exchanges (panel
+steps: the triangular solve of Alg. It-Inv-TRSM with whole inverted diagonal
+blocks) through the C ABI against the CPU oracle's Doolittle definition, on
+the same seeded, strictly column diagonally dominant matrices (the class the
+no-exchange factorization is for; cond(A) is small there).  Tolerance: 1e-12
+relative Frobenius error for L, U and the inverted diagonal blocks."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_01855_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1612_01855_amd import trsm
+    return trsm
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def gpu_lu(torch, T, A, nb=0, lda=None, pad=7.0):
+    n = A.shape[0]
+    lda = n if lda is None else lda
+    Ah = np.full((n, lda), pad)
+    Ah[:, :n] = A
+    Ad = torch.from_numpy(Ah).cuda()
+    f = T.LU(n, nb, device="cuda")
+    log(f"lu n={n} nb={f.nb} lda={lda}")
+    f.factor(Ad[:, :n] if lda == n else Ad.as_strided((n, n), (lda, 1)))
+    torch.cuda.synchronize()
+    full = Ad.cpu().numpy()
+    F = full[:, :n]
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    return L, U, full, f
+
+
+@pytest.mark.parametrize("n,nb", [(1, 0), (63, 0), (64, 64), (65, 64), (200, 64), (300, 128),
+                                  (1000, 128), (1100, 256), (1536, 512), (2048, 256)])
+def test_factor_matches_oracle(torch, T, n, nb):
+    A = gen.diag_dominant(n, n + 5)
+    L, U, _, f = gpu_lu(torch, T, A, nb)
+    assert f.check() == (T.OK, -1)
+    Lr, Ur, fail = oracle.lu_nopiv(A)
+    assert fail == -1
+    el, eu = oracle.rel_fro_err(L, Lr), oracle.rel_fro_err(U, Ur)
+    log(f"  rel err L {el:.2e} U {eu:.2e}")
+    assert el <= TOL64 and eu <= TOL64
+
+
+@pytest.mark.parametrize("n,nb", [(300, 128), (1100, 256), (777, 64)])
+def test_inverted_blocks_match_oracle(torch, T, n, nb):
+    A = gen.diag_dominant(n, 3 * n)
+    _, _, _, f = gpu_lu(torch, T, A, nb)
+    Lr, Ur, _ = oracle.lu_nopiv(A)
+    nbu = f.nb
+    VL, VU = f.linv_blocks().cpu().numpy(), f.uinv_blocks().cpu().numpy()
+    for j in range(VL.shape[0]):
+        s0 = j * nbu
+        s = min(nbu, n - s0)
+        il = oracle.inv_lower(Lr[s0:s0 + s, s0:s0 + s])
+        iu = oracle.inv_lower(np.ascontiguousarray(Ur[s0:s0 + s, s0:s0 + s].T)).T
+        assert oracle.rel_fro_err(VL[j][:s, :s], il) <= TOL64
+        assert oracle.rel_fro_err(VU[j][:s, :s], iu) <= TOL64
+        assert np.all(VL[j][np.triu_indices(nbu, 1)] == 0.0)
+        assert np.all(VU[j][np.tril_indices(nbu, -1)] == 0.0)
+        if s < nbu:     # ragged last block: identity padding
+            assert np.array_equal(VL[j][s:, s:], np.eye(nbu - s))
+            assert np.array_equal(VU[j][s:, s:], np.eye(nbu - s))
+
+
+def test_leaf_sizes_are_exact_on_integer_factors(torch, T):
+    # n <= 64: one LDS leaf, no inverse on the factor's path; every
+    # intermediate is an integer or an exact division by a power of two
+    L0 = gen.int_unit_lower_small(60, 4)
+    U0 = gen.int_upper_pow2(60, 5)
+    A = (L0.astype(np.int64) @ U0.astype(np.int64)).astype(np.float64)
+    L, U, _, f = gpu_lu(torch, T, A)
+    assert f.check() == (T.OK, -1)
+    assert np.array_equal(L, L0) and np.array_equal(U, U0)
+
+
+@pytest.mark.parametrize("n,nb,bad", [(50, 0, 17), (300, 64, 0), (300, 64, 200),
+                                      (1000, 256, 999), (1000, 256, 512)])
+def test_bad_pivot_reports_the_row(torch, T, n, nb, bad):
+    A = gen.diag_dominant(n, 6)
+    A[bad, bad] = np.nan        # pivot `bad` is NaN; earlier pivots do not see row/column bad
+    _, _, _, f = gpu_lu(torch, T, A, nb)
+    assert f.check() == (T.ESINGULAR, bad)
+    if bad == 0:
+        A[0, 0] = 0.0
+        _, _, _, f = gpu_lu(torch, T, A, nb)
+        assert f.check() == (T.ESINGULAR, 0)
+
+
+def test_padded_leading_dimension(torch, T):
+    n, lda = 700, 733
+    A = gen.diag_dominant(n, 2)
+    L, U, full, f = gpu_lu(torch, T, A, 128, lda=lda, pad=7.0)
+    assert f.check() == (T.OK, -1)
+    Lr, Ur, _ = oracle.lu_nopiv(A)
+    assert oracle.rel_fro_err(L, Lr) <= TOL64 and oracle.rel_fro_err(U, Ur) <= TOL64
+    assert np.all(full[:, n:] == 7.0)
+
+
+def test_factor_then_solve_with_its_blocks(torch, T):
+    # the Linv blocks are a TRSM_F64 plan's (n0 = nb): L Y = B with the
+    # factored A as the plan's L (unit diagonal carried by the blocks)
+    n, k, nb = 1100, 40, 256
+    A = gen.diag_dominant(n, 9)
+    B = gen.rhs(n, k, 9)
+    Ad = torch.from_numpy(A.copy()).cuda()
+    f = T.LU(n, nb, device="cuda")
+    f.factor(Ad)
+    s = T.Solver.create(n, k, "f64", n0=nb)
+    try:
+        assert s.info.linv_bytes == f.inv_bytes
+        Bd = torch.from_numpy(B).cuda()
+        Yd = torch.empty_like(Bd)
+        T.trsm_solve(s.plan, Ad.data_ptr(), n, f.linv_ptr, Bd.data_ptr(), k, Yd.data_ptr(), k,
+                     s.workspace_ptr, torch.cuda.current_stream().cuda_stream, None)
+        torch.cuda.synchronize()
+    finally:
+        s.close()
+    F = Ad.cpu().numpy()
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    Y = Yd.cpu().numpy()
+    assert oracle.rel_fro_err(Y, oracle.trsm(L, B)) <= TOL64
+    X = np.linalg.solve(U, Y)
+    assert oracle.rel_fro_err(X, np.linalg.solve(A, B)) <= TOL64
+
+
+def test_graph_capture_replays(torch, T):
+    n, nb = 900, 128
+    A0 = torch.from_numpy(gen.diag_dominant(n, 21)).cuda()
+    Ad = A0.clone()
+    f = T.LU(n, nb, device="cuda")
+    f.factor(Ad)
+    torch.cuda.synchronize()
+    eager = Ad.clone()
+    s = torch.cuda.Stream()
+    Ag = A0.clone()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            T.trsm_lu_factor(n, Ag.data_ptr(), n, nb, f.linv_ptr, f.uinv_ptr, f.workspace_ptr,
+                             s.cuda_stream)
+    for _ in range(3):
+        Ag.copy_(A0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ag, eager)
+        assert f.check() == (T.OK, -1)
+
+
+def test_spd_input_agrees_with_cholesky(torch, T):
+    # on a symmetric positive definite matrix, L U = C C^T: U = diag(c) C^T
+    n = 1000
+    A = gen.spd(n, 4)
+    L, U, _, f = gpu_lu(torch, T, A, 256)
+    assert f.check() == (T.OK, -1)
+    C = T.cholesky(torch.from_numpy(A).cuda(), nb=256).cpu().numpy()
+    d = np.diag(C)
+    assert oracle.rel_fro_err(U, d[:, None] * C.T) <= TOL64
+    assert oracle.rel_fro_err(L, C / d[None, :]) <= TOL64
+
+
+def test_empty(torch, T):
+    f = T.LU(0, 0, device="cuda")
+    Ad = torch.zeros((1, 1), dtype=torch.float64, device="cuda")
+    T.trsm_lu_factor(0, Ad.data_ptr(), 1, 0, f.linv_ptr, f.uinv_ptr, f.workspace_ptr, 0)
+    assert f.check() == (T.OK, -1)
