@@ -269,6 +269,54 @@ def cholesky_bench(args, torch, T, gen, dev, emit):
         torch.cuda.empty_cache()
 
 
+def lu_bench(args, torch, T, gen, dev, emit):
+    """Blocked LU without row exchanges (binary64) on strictly column
+    diagonally dominant matrices: median of 3 timed factorizations after a warm
+    one, flops 2 n^3 / 3, backward error ||A - L U|| / ||A|| on 64 sampled
+    rows."""
+    sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
+    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512)
+    for n in sizes:
+        g = torch.Generator(device=dev).manual_seed(args.seed)
+        A0 = torch.rand((n, n), generator=g, dtype=torch.float64, device=dev) * 2.0 - 1.0
+        A0.diagonal().zero_()
+        A0.diagonal().add_(A0.abs().sum(dim=0) + 1.0)
+        for nb in blocks:
+            if nb > n // 4:
+                continue
+            f = T.LU(n, nb, device=dev)
+            A = torch.empty_like(A0)
+            times = []
+            for it in range(4):
+                A.copy_(A0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                f.factor(A)
+                e1.record()
+                torch.cuda.synchronize()
+                if it:
+                    times.append(e0.elapsed_time(e1))
+            st, idx = f.check()
+            gcpu = torch.Generator().manual_seed(args.seed)
+            rows = torch.randint(0, n, (64,), generator=gcpu).to(dev)
+            Ar = A.index_select(0, rows)
+            cols = torch.arange(n, device=dev)
+            Lr = torch.where(cols[None, :] < rows[:, None], Ar, torch.zeros_like(Ar))
+            Lr.scatter_(1, rows[:, None], 1.0)           # rows of L: unit diagonal
+            R = A0.index_select(0, rows) - Lr @ torch.triu(A)
+            be = float(torch.linalg.norm(R).item() / torch.linalg.norm(A0.index_select(0, rows)).item())
+            ms = sorted(times)[1]
+            tf = 2.0 * float(n) ** 3 / 3.0 / (ms * 1e-3) / 1e12
+            emit({"suite": "lu_nopiv", "n": n, "nb": int(f.nb), "auto": nb == 0,
+                  "ms": round(ms, 3), "tflops_2n3_3": round(tf, 2),
+                  "frac_peak": round(tf / PEAK["f64"], 4), "status": T.status_string(st),
+                  "sampled_backward_error": be})
+            log(f"suite lu n={n} nb={f.nb}: {ms:.2f} ms {tf:.2f} TF backward {be:.2e}")
+            del f, A, Ar, Lr, R
+        del A0
+        torch.cuda.empty_cache()
+
+
 def run_suite(args, torch, T, gen, dev):
     """The workload sweeps: n0 sweep and the recursive baseline at n = k = 8192
     (binary64 and binary32), the n/k sweep at n = 16384, and the hard factor in
@@ -363,8 +411,9 @@ def run_suite(args, torch, T, gen, dev):
           "rate_sweep": res.get("rate_sweep")})
     torch.cuda.empty_cache()
 
-    # blocked Cholesky factorization with the inverted-block panel solve
+    # blocked Cholesky and LU (no row exchanges) with inverted-block panel solves
     cholesky_bench(args, torch, T, gen, dev, emit)
+    lu_bench(args, torch, T, gen, dev, emit)
 
     # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)
     n = k = 16384
@@ -432,18 +481,22 @@ def main():
                     help="instead of the headline step, run the workload sweeps (one JSON line each)")
     ap.add_argument("--cholesky", action="store_true",
                     help="instead of the headline step, run only the Cholesky sweep of the suite")
-    ap.add_argument("--chol-n", type=int, default=0, help="--cholesky: this n only")
-    ap.add_argument("--chol-nb", type=int, default=None, help="--cholesky: this block size only")
+    ap.add_argument("--lu", action="store_true",
+                    help="instead of the headline step, run only the LU (no row exchanges) sweep")
+    ap.add_argument("--chol-n", type=int, default=0, help="--cholesky / --lu: this n only")
+    ap.add_argument("--chol-nb", type=int, default=None,
+                    help="--cholesky / --lu: this block size only")
     args = ap.parse_args()
 
-    if args.suite or args.cholesky:
+    if args.suite or args.cholesky or args.lu:
         import torch
         from paper_1612_01855_amd import inputs as gen
         from paper_1612_01855_amd import trsm as T
         assert torch.cuda.is_available(), "bench.py needs a GPU"
-        if args.cholesky:
-            cholesky_bench(args, torch, T, gen, torch.device("cuda:0"),
-                           lambda rec: print(json.dumps(rec), flush=True))
+        if args.cholesky or args.lu:
+            bench_fn = cholesky_bench if args.cholesky else lu_bench
+            bench_fn(args, torch, T, gen, torch.device("cuda:0"),
+                     lambda rec: print(json.dumps(rec), flush=True))
         else:
             run_suite(args, torch, T, gen, torch.device("cuda:0"))
         return

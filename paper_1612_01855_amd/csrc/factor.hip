@@ -215,76 +215,133 @@ __global__ void chol_init_kernel(double* __restrict__ V, int64_t n, int64_t nb, 
 }
 
 // LU leaf: the s x s (s <= 64) diagonal block D is factored without row
-// exchanges in LDS by 256 threads, right-looking, step j:
-//   u_jc = d_jc (c >= j, already updated),  l_ij = d_ij / u_jj (i > j),
-//   d_ic -= l_ij u_jc (i, c > j);
-// then threads 0..63 form column t of L's unit lower inverse and threads
-// 64..127 column t of U's inverse, by substitution on the identity:
-//   x_rt = -sum_{p<r} l_rp x_pt (r > t, x_tt = 1),
-//   y_rt = -(sum_{p>r} u_rp y_pt) / u_rr (r < t, y_tt = 1 / u_tt),
-// every lane walking the same (r, p) so that l_rp and u_rp are LDS
-// broadcasts.  L (strictly lower) and U go back to D, the inverses to VL (unit
-// lower, diagonal stored) and VU (upper), ld ldv, nothing written on their
-// other side.  A zero or non-finite pivot records its global row in *bad (the
-// smallest one wins) and is replaced by 1 in the divisions.
-__global__ __launch_bounds__(256) void lu_leaf_kernel(double* __restrict__ D, int64_t ldd, int s,
-                                                      double* __restrict__ VL,
-                                                      double* __restrict__ VU, int64_t ldv,
-                                                      int64_t row0, unsigned long long* bad) {
-  __shared__ double S[kLeaf][kLeaf + 1];
-  __shared__ double XL[kLeaf][kLeaf + 1];
-  __shared__ double XU[kLeaf][kLeaf + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < kLeaf * kLeaf; e += 256) {
-    const int i = e / kLeaf, j = e % kLeaf;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < s && j < s) v = D[(int64_t)i * ldd + j];
-    S[i][j] = v;
+// exchanges by four waves, right-looking, step j (u_jj the pivot):
+//   l_ij = d_ij / u_jj (i > j),  u_jc = d_jc (c >= j),  d_ic -= l_ij u_jc (i, c > j).
+// Wave 0 holds row i in lane i and publishes column j of L in LDS; wave 1
+// holds column c in lane c and publishes row j of U; after one barrier each
+// takes the other's half for its update (both compute the same products, so
+// their U parts stay bitwise equal; wave 1 never scales its entries below the
+// diagonal, which nothing reads), while wave 2 (column t of L^{-1}, unit diagonal)
+// and wave 3 (column t of (U^T)^{-1}, i.e. row t of U^{-1}) take step j of
+// their substitutions from the same two published vectors:
+//   x_rt -= l_rj x_jt (r > j);   z_jt /= u_jj,  z_rt -= u_jr z_jt (r > j).
+// Positions past s hold the identity.  L (strictly lower) and U go back to
+// D, the inverses to VL (unit lower, diagonal stored) and VU (upper), ld ldv,
+// nothing written on their other side.  A zero or non-finite pivot records
+// its global row in *bad (the smallest one wins) and is replaced by 1 in the
+// divisions of L.  LDS reads come in 16-byte pairs issued ahead of their use.
+__global__ __launch_bounds__(4 * kLeaf) void lu_leaf_kernel(double* __restrict__ D,
+                                                            int64_t ldd, int s,
+                                                            double* __restrict__ VL,
+                                                            double* __restrict__ VU,
+                                                            int64_t ldv, int64_t row0,
+                                                            unsigned long long* bad) {
+  __shared__ __attribute__((aligned(16))) double Lc[kLeaf][kLdc];   // [j][r]: l_rj
+  __shared__ __attribute__((aligned(16))) double Uc[kLeaf][kLdc];   // [j][c]: u_jc
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  const int tid = threadIdx.x, w = tid / kLeaf, i = tid % kLeaf;
+  // coalesced load staged in Lc, all loads of a thread issued first
+  {
+    double v[kLeaf / 4];
+#pragma unroll
+    for (int q = 0; q < kLeaf / 4; ++q) {
+      const int r = 4 * q + w;
+      v[q] = (r < s && i < s) ? D[(int64_t)r * ldd + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLeaf / 4; ++q) {
+      const int r = 4 * q + w;
+      Lc[r][i] = (r >= s && r == i) ? 1.0 : v[q];
+    }
   }
   __syncthreads();
-  const int row = t % kLeaf, cg = t / kLeaf;
+  // wave 0: row i; wave 1: column i; waves 2, 3: column i of the identity
+  double a[kLeaf];
+  if (w == 0) {
+#pragma unroll
+    for (int c = 0; c < kLeaf; c += 2) {
+      const D2 v = *reinterpret_cast<const D2*>(&Lc[i][c]);
+      a[c] = v.x;
+      a[c + 1] = v.y;
+    }
+  } else if (w == 1) {
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) a[r] = Lc[r][i];
+  } else {
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) a[r] = (r == i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
   int first = kLeaf;
-  for (int j = 0; j < s; ++j) {
-    double piv = S[j][j];
-    const bool ok = (piv != 0.0) && isfinite(piv);
-    first = (!ok && first == kLeaf) ? j : first;
-    piv = ok ? piv : 1.0;
-    if (t > j && t < s) S[t][j] = S[t][j] / piv;
-    __syncthreads();
-    if (row > j && row < s) {
-      const double lij = S[row][j];
-      for (int c = j + 1 + cg; c < s; c += 4) S[row][c] -= lij * S[j][c];
+  // a[c] -= m * P[c] for c > j, P a published LDS vector read in pairs
+  auto axpy = [&](const double* P, double m, int j) {
+    const int q0 = (j + 1) / 2;
+    D2 buf[kLeaf / 2];
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2 && q < q0 + kAhead; ++q)
+      buf[q] = *reinterpret_cast<const D2*>(P + 2 * q);
+#pragma unroll
+    for (int q = q0; q < kLeaf / 2; ++q) {
+      if (q + kAhead < kLeaf / 2) buf[q + kAhead] = *reinterpret_cast<const D2*>(P + 2 * (q + kAhead));
+      if (2 * q > j) a[2 * q] = fma(-m, buf[q].x, a[2 * q]);
+      a[2 * q + 1] = fma(-m, buf[q].y, a[2 * q + 1]);
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < kLeaf; ++j) {
+    if (w == 0) {
+      double piv = lane_value(a[j], j);
+      const bool ok = (piv != 0.0) && isfinite(piv);
+      first = (!ok && first == kLeaf) ? j : first;
+      piv = ok ? piv : 1.0;
+      const double l = (i > j) ? a[j] / piv : 0.0;
+      a[j] = (i > j) ? l : a[j];
+      Lc[j][i] = l;
+    } else if (w == 1) {
+      Uc[j][i] = a[j];
     }
     __syncthreads();
+    if (w == 0) {
+      axpy(&Uc[j][0], (i > j) ? a[j] : 0.0, j);            // row i: -= l_ij u_j.
+    } else if (w == 1) {
+      const double u = (i > j) ? a[j] : 0.0;               // column i: -= l_.j u_ji
+#pragma unroll
+      for (int q = (j + 1) / 2; q < kLeaf / 2; ++q) {
+        const D2 v = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
+        if (2 * q > j) a[2 * q] = fma(-v.x, u, a[2 * q]);
+        a[2 * q + 1] = fma(-v.y, u, a[2 * q + 1]);
+      }
+    } else if (w == 2) {
+      axpy(&Lc[j][0], a[j], j);                            // x_r -= l_rj x_j
+    } else {
+      a[j] = a[j] / Uc[j][j];                              // z_j /= u_jj
+      axpy(&Uc[j][0], a[j], j);                            // z_r -= u_jr z_j
+    }
   }
-  if (t == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
-  if (t < kLeaf) {
-    for (int r = 0; r < kLeaf; ++r) XL[r][t] = (r == t) ? 1.0 : 0.0;
-    for (int r = 1; r < kLeaf; ++r) {
-      if (t < r) {
-        double acc = 0.0;
-        for (int p = 0; p < r; ++p) acc += S[r][p] * XL[p][t];
-        XL[r][t] = -acc;
-      }
-    }
-  } else if (t < 2 * kLeaf) {
-    const int tc = t - kLeaf;
-    for (int r = 0; r < kLeaf; ++r) XU[r][tc] = (r == tc) ? 1.0 / S[tc][tc] : 0.0;
-    for (int r = kLeaf - 2; r >= 0; --r) {
-      if (tc > r) {
-        double acc = 0.0;
-        for (int p = r + 1; p < kLeaf; ++p) acc += S[r][p] * XU[p][tc];
-        XU[r][tc] = -acc / S[r][r];
-      }
-    }
+  if (tid == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
+  __syncthreads();
+  // L and U rows (wave 0) to Lc, L^{-1} columns (wave 2) to Uc; then stores
+  if (w == 0) {
+#pragma unroll
+    for (int c = 0; c < kLeaf; ++c) Lc[i][c] = a[c];
+  } else if (w == 2) {
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) Uc[r][i] = a[r];
   }
   __syncthreads();
-  for (int e = t; e < kLeaf * kLeaf; e += 256) {
-    const int i = e / kLeaf, j = e % kLeaf;
-    if (i < s && j < s) D[(int64_t)i * ldd + j] = S[i][j];
-    if (j <= i) VL[(int64_t)i * ldv + j] = XL[i][j];
-    if (j >= i) VU[(int64_t)i * ldv + j] = XU[i][j];
+  for (int r = w; r < kLeaf; r += 4) {
+    if (r < s && i < s) D[(int64_t)r * ldd + i] = Lc[r][i];
+    if (i <= r) VL[(int64_t)r * ldv + i] = Uc[r][i];
   }
+  __syncthreads();
+  // U^{-1} rows (wave 3: lane t holds row t) to Lc, then stores
+  if (w == 3) {
+#pragma unroll
+    for (int c = 0; c < kLeaf; ++c) Lc[i][c] = a[c];
+  }
+  __syncthreads();
+  for (int r = w; r < kLeaf; r += 4)
+    if (i >= r) VU[(int64_t)r * ldv + i] = Lc[r][i];
 }
 
 struct Ctx {
@@ -512,7 +569,7 @@ trsm_status lu_factor_diag(const Ctx& c, int64_t r0, int64_t s, double* VL, doub
   const int64_t lda = c.lda, nb = c.nb;
   double* D = c.A + r0 * lda + r0;
   if (s <= kLeaf) {
-    lu_leaf_kernel<<<1, 256, 0, c.s>>>(D, lda, (int)s, VL, VU, nb, r0, c.bad);
+    lu_leaf_kernel<<<1, 4 * kLeaf, 0, c.s>>>(D, lda, (int)s, VL, VU, nb, r0, c.bad);
     CHOL_HIP(hipGetLastError());
     return TRSM_OK;
   }
