@@ -277,10 +277,7 @@ def lu_bench(args, torch, T, gen, dev, emit):
     sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
     blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512)
     for n in sizes:
-        g = torch.Generator(device=dev).manual_seed(args.seed)
-        A0 = torch.rand((n, n), generator=g, dtype=torch.float64, device=dev) * 2.0 - 1.0
-        A0.diagonal().zero_()
-        A0.diagonal().add_(A0.abs().sum(dim=0) + 1.0)
+        A0 = gen.diag_dominant_on(torch, dev, n, args.seed)
         for nb in blocks:
             if nb > n // 4:
                 continue

@@ -32,9 +32,16 @@ FLAGS = [
 ]
 
 
+# Per-source additions.  The factorization leaves keep a row or column of a
+# 64 x 64 block in registers, which needs their fully unrolled step loops;
+# the four-role LU leaf exceeds the compiler's default size limit for a
+# requested full unroll.
+EXTRA = {"factor.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(ln for ln in r.stderr.splitlines() if noise not in ln)

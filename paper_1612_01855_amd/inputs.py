@@ -200,6 +200,19 @@ def diag_dominant(n: int, seed: int, margin: float = 1.0) -> np.ndarray:
     return np.ascontiguousarray(A)
 
 
+def diag_dominant_on(torch, device, n: int, seed: int, margin: float = 1.0):
+    """diag_dominant's construction at sizes where the host generator is slow:
+    off-diagonal entries ~ U[-1, 1] from torch's seeded generator on `device`,
+    a_jj = margin + sum_{i != j} |a_ij| (positive diagonal).  A float64
+    tensor; not bit-identical to the host version (a different stream of
+    random numbers)."""
+    g = torch.Generator(device=device).manual_seed(seed)
+    A = torch.rand((n, n), generator=g, dtype=torch.float64, device=device) * 2.0 - 1.0
+    A.diagonal().zero_()
+    A.diagonal().add_(A.abs().sum(dim=0) + margin)
+    return A
+
+
 def int_unit_lower_small(n: int, seed: int, lo: int = -2, hi: int = 2) -> np.ndarray:
     """Unit lower-triangular integer matrix, strict lower entries in {lo..hi}."""
     g = rng(seed)

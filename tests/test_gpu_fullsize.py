@@ -261,3 +261,49 @@ def test_cholesky_factor_n16384(torch, T, ratio):
     be = float(torch.linalg.norm(R).item() / torch.linalg.norm(A0.index_select(0, idx)).item())
     log(f"  sampled backward error {be:.2e}")
     assert be <= 4 * n * 2.0 ** -53
+
+
+def test_lu_nopiv_factor_n16384(torch, T):
+    """The LU factorization without row exchanges at n = 16384 (benchmark
+    configuration, default block size) on a strictly column diagonally
+    dominant matrix, checked piecewise: the leading 1024 x 1024 blocks of L
+    and U are the oracle's factors of A's leading block; sampled rows of L
+    satisfy L(i, 0:i) U(0:i, 0:i) = A(i, 0:i) (the oracle's substitution with
+    U^T); a sampled pair of inverted diagonal blocks are the inverses of L's
+    and U's blocks (oracle); sampled rows of A - L U are at rounding level."""
+    n = 16384
+    A0 = gen.diag_dominant_on(torch, "cuda", n, 23)
+    Ad = A0.clone()
+    f = T.LU(n, 0, device="cuda")
+    f.factor(Ad)
+    torch.cuda.synchronize()
+    assert f.check() == (T.OK, -1)
+    lead = 1024
+    Lr, Ur, fail = oracle.lu_nopiv(A0[:lead, :lead].cpu().numpy())
+    F = Ad[:lead, :lead].cpu().numpy()
+    el = oracle.rel_fro_err(np.tril(F, -1) + np.eye(lead), Lr)
+    eu = oracle.rel_fro_err(np.triu(F), Ur)
+    log(f"full size lu: leading block rel err L {el:.2e} U {eu:.2e}")
+    assert fail == -1 and el <= TOL64 and eu <= TOL64
+    for i in np.sort(np.random.default_rng(4).choice(np.arange(lead, n), 5, replace=False)):
+        Ut = np.ascontiguousarray(torch.triu(Ad[:i, :i]).t().cpu().numpy())
+        x = oracle.trsm(Ut, A0[i, :i].cpu().numpy()[:, None])[:, 0]
+        row = Ad[i, :i].cpu().numpy()
+        e = np.linalg.norm(row - x) / np.linalg.norm(x)
+        log(f"  row {i}: rel err {e:.2e}")
+        assert e <= TOL64
+    j, nb = 11, f.nb
+    blk = Ad[j * nb:(j + 1) * nb, j * nb:(j + 1) * nb].cpu().numpy()
+    il = oracle.inv_lower(np.tril(blk, -1) + np.eye(nb))
+    iu = oracle.inv_lower(np.ascontiguousarray(np.triu(blk).T)).T
+    assert oracle.rel_fro_err(f.linv_blocks()[j].cpu().numpy(), il) <= TOL64
+    assert oracle.rel_fro_err(f.uinv_blocks()[j].cpu().numpy(), iu) <= TOL64
+    rows = torch.from_numpy(np.sort(np.random.default_rng(6).choice(n, 64, replace=False))).cuda()
+    Ar = Ad.index_select(0, rows)
+    cols = torch.arange(n, device="cuda")
+    Lrows = torch.where(cols[None, :] < rows[:, None], Ar, torch.zeros_like(Ar))
+    Lrows.scatter_(1, rows[:, None], 1.0)
+    R = A0.index_select(0, rows) - Lrows @ torch.triu(Ad)
+    be = float(torch.linalg.norm(R).item() / torch.linalg.norm(A0.index_select(0, rows)).item())
+    log(f"  sampled backward error {be:.2e}")
+    assert be <= 4 * n * 2.0 ** -53
