@@ -221,10 +221,13 @@ __global__ void chol_init_kernel(double* __restrict__ V, int64_t n, int64_t nb, 
 // holds column c in lane c and publishes row j of U; after one barrier each
 // takes the other's half for its update (both compute the same products, so
 // their U parts stay bitwise equal; wave 1 never scales its entries below the
-// diagonal, which nothing reads), while wave 2 (column t of L^{-1}, unit diagonal)
-// and wave 3 (column t of (U^T)^{-1}, i.e. row t of U^{-1}) take step j of
-// their substitutions from the same two published vectors:
+// diagonal, which nothing reads), while wave 2 (column t of L^{-1}, unit
+// diagonal) and wave 3 (column t of (U^T)^{-1}, i.e. row t of U^{-1}) take
+// step j of their substitutions from the same two published vectors:
 //   x_rt -= l_rj x_jt (r > j);   z_jt /= u_jj,  z_rt -= u_jr z_jt (r > j).
+// Every wave consumes step j's vectors within step j, so two LDS slots per
+// vector suffice (2 KB in all: the leaf fits beside the trailing products'
+// workgroups); the block goes between global memory and registers directly.
 // Positions past s hold the identity.  L (strictly lower) and U go back to
 // D, the inverses to VL (unit lower, diagonal stored) and VU (upper), ld ldv,
 // nothing written on their other side.  A zero or non-finite pivot records
@@ -236,42 +239,24 @@ __global__ __launch_bounds__(4 * kLeaf) void lu_leaf_kernel(double* __restrict__
                                                             double* __restrict__ VU,
                                                             int64_t ldv, int64_t row0,
                                                             unsigned long long* bad) {
-  __shared__ __attribute__((aligned(16))) double Lc[kLeaf][kLdc];   // [j][r]: l_rj
-  __shared__ __attribute__((aligned(16))) double Uc[kLeaf][kLdc];   // [j][c]: u_jc
+  __shared__ __attribute__((aligned(16))) double Lr[2][kLdc];   // slot: l_rj, column j of L
+  __shared__ __attribute__((aligned(16))) double Ur[2][kLdc];   // slot: u_jc, row j of U
   typedef double D2 __attribute__((ext_vector_type(2)));
   const int tid = threadIdx.x, w = tid / kLeaf, i = tid % kLeaf;
-  // coalesced load staged in Lc, all loads of a thread issued first
-  {
-    double v[kLeaf / 4];
-#pragma unroll
-    for (int q = 0; q < kLeaf / 4; ++q) {
-      const int r = 4 * q + w;
-      v[q] = (r < s && i < s) ? D[(int64_t)r * ldd + i] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kLeaf / 4; ++q) {
-      const int r = 4 * q + w;
-      Lc[r][i] = (r >= s && r == i) ? 1.0 : v[q];
-    }
-  }
-  __syncthreads();
   // wave 0: row i; wave 1: column i; waves 2, 3: column i of the identity
   double a[kLeaf];
   if (w == 0) {
 #pragma unroll
-    for (int c = 0; c < kLeaf; c += 2) {
-      const D2 v = *reinterpret_cast<const D2*>(&Lc[i][c]);
-      a[c] = v.x;
-      a[c + 1] = v.y;
-    }
+    for (int c = 0; c < kLeaf; ++c)
+      a[c] = (i < s && c < s) ? D[(int64_t)i * ldd + c] : (c == i ? 1.0 : 0.0);
   } else if (w == 1) {
 #pragma unroll
-    for (int r = 0; r < kLeaf; ++r) a[r] = Lc[r][i];
+    for (int r = 0; r < kLeaf; ++r)
+      a[r] = (r < s && i < s) ? D[(int64_t)r * ldd + i] : (r == i ? 1.0 : 0.0);
   } else {
 #pragma unroll
     for (int r = 0; r < kLeaf; ++r) a[r] = (r == i) ? 1.0 : 0.0;
   }
-  __syncthreads();
   int first = kLeaf;
   // a[c] -= m * P[c] for c > j, P a published LDS vector read in pairs
   auto axpy = [&](const double* P, double m, int j) {
@@ -289,6 +274,7 @@ __global__ __launch_bounds__(4 * kLeaf) void lu_leaf_kernel(double* __restrict__
   };
 #pragma unroll
   for (int j = 0; j < kLeaf; ++j) {
+    const int slot = j & 1;
     if (w == 0) {
       double piv = lane_value(a[j], j);
       const bool ok = (piv != 0.0) && isfinite(piv);
@@ -296,52 +282,44 @@ __global__ __launch_bounds__(4 * kLeaf) void lu_leaf_kernel(double* __restrict__
       piv = ok ? piv : 1.0;
       const double l = (i > j) ? a[j] / piv : 0.0;
       a[j] = (i > j) ? l : a[j];
-      Lc[j][i] = l;
+      Lr[slot][i] = l;
     } else if (w == 1) {
-      Uc[j][i] = a[j];
+      Ur[slot][i] = a[j];
     }
     __syncthreads();
     if (w == 0) {
-      axpy(&Uc[j][0], (i > j) ? a[j] : 0.0, j);            // row i: -= l_ij u_j.
+      axpy(&Ur[slot][0], (i > j) ? a[j] : 0.0, j);         // row i: -= l_ij u_j.
     } else if (w == 1) {
       const double u = (i > j) ? a[j] : 0.0;               // column i: -= l_.j u_ji
 #pragma unroll
       for (int q = (j + 1) / 2; q < kLeaf / 2; ++q) {
-        const D2 v = *reinterpret_cast<const D2*>(&Lc[j][2 * q]);
+        const D2 v = *reinterpret_cast<const D2*>(&Lr[slot][2 * q]);
         if (2 * q > j) a[2 * q] = fma(-v.x, u, a[2 * q]);
         a[2 * q + 1] = fma(-v.y, u, a[2 * q + 1]);
       }
     } else if (w == 2) {
-      axpy(&Lc[j][0], a[j], j);                            // x_r -= l_rj x_j
+      axpy(&Lr[slot][0], a[j], j);                         // x_r -= l_rj x_j
     } else {
-      a[j] = a[j] / Uc[j][j];                              // z_j /= u_jj
-      axpy(&Uc[j][0], a[j], j);                            // z_r -= u_jr z_j
+      a[j] = a[j] / Ur[slot][j];                           // z_j /= u_jj
+      axpy(&Ur[slot][0], a[j], j);                         // z_r -= u_jr z_j
     }
   }
   if (tid == 0 && first < s) atomicMin(bad, (unsigned long long)(row0 + first));
-  __syncthreads();
-  // L and U rows (wave 0) to Lc, L^{-1} columns (wave 2) to Uc; then stores
   if (w == 0) {
+    if (i < s) {
 #pragma unroll
-    for (int c = 0; c < kLeaf; ++c) Lc[i][c] = a[c];
+      for (int c = 0; c < kLeaf; ++c)
+        if (c < s) D[(int64_t)i * ldd + c] = a[c];
+    }
   } else if (w == 2) {
 #pragma unroll
-    for (int r = 0; r < kLeaf; ++r) Uc[r][i] = a[r];
-  }
-  __syncthreads();
-  for (int r = w; r < kLeaf; r += 4) {
-    if (r < s && i < s) D[(int64_t)r * ldd + i] = Lc[r][i];
-    if (i <= r) VL[(int64_t)r * ldv + i] = Uc[r][i];
-  }
-  __syncthreads();
-  // U^{-1} rows (wave 3: lane t holds row t) to Lc, then stores
-  if (w == 3) {
+    for (int r = 0; r < kLeaf; ++r)
+      if (r >= i) VL[(int64_t)r * ldv + i] = a[r];
+  } else if (w == 3) {
 #pragma unroll
-    for (int c = 0; c < kLeaf; ++c) Lc[i][c] = a[c];
+    for (int c = 0; c < kLeaf; ++c)
+      if (c >= i) VU[(int64_t)i * ldv + c] = a[c];
   }
-  __syncthreads();
-  for (int r = w; r < kLeaf; r += 4)
-    if (i >= r) VU[(int64_t)r * ldv + i] = Lc[r][i];
 }
 
 struct Ctx {
