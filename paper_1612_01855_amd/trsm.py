@@ -398,7 +398,19 @@ def _stream_handle(torch, device) -> int:
 def _ld(t) -> int:
     if t.dim() != 2 or t.stride(1) != 1:
         raise ValueError("matrices must be 2-D with unit column stride (row-major)")
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError("matrix rows overlap (row stride below the column count)")
     return max(t.stride(0), t.shape[1], 1)
+
+
+def _dev(t, dtype, what: str) -> int:
+    """Device pointer of a CUDA tensor of the given dtype; a host tensor or a
+    wrong element type is refused before anything reaches the library."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what} must be a CUDA (HIP device) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
 
 
 @dataclass
@@ -432,18 +444,23 @@ class Solver:
     def workspace_ptr(self) -> int:
         return self._aligned(self.workspace)
 
+    def _dtype(self):
+        import torch
+        return torch.float32 if self.info.precision == F32 else torch.float64
+
     def invert(self, L) -> None:
         import torch
-        trsm_invert_diag(self.plan, L.data_ptr(), _ld(L), self.linv_ptr,
+        trsm_invert_diag(self.plan, _dev(L, self._dtype(), "L"), _ld(L), self.linv_ptr,
                          _stream_handle(torch, L.device))
 
     def solve(self, L, B, X=None, info: Optional[Info] = None) -> object:
         import torch
         if X is None:
             X = torch.empty_like(B)
-        trsm_solve(self.plan, L.data_ptr(), _ld(L), self.linv_ptr, B.data_ptr(), _ld(B),
-                   X.data_ptr(), _ld(X), self.workspace_ptr, _stream_handle(torch, B.device),
-                   info)
+        dt = self._dtype()
+        trsm_solve(self.plan, _dev(L, dt, "L"), _ld(L), self.linv_ptr, _dev(B, dt, "B"), _ld(B),
+                   _dev(X, dt, "X"), _ld(X), self.workspace_ptr,
+                   _stream_handle(torch, B.device), info)
         return X
 
     def last_error(self):
@@ -484,9 +501,9 @@ class Cholesky:
     def factor(self, A) -> None:
         """In place: the lower triangle of the float64 tensor A becomes L."""
         import torch
-        if A.dtype != torch.float64 or A.shape[0] != self.n or A.shape[1] < self.n:
+        if A.shape[0] != self.n or A.shape[1] < self.n:
             raise ValueError("A must be an n x n float64 tensor")
-        trsm_chol_factor(self.n, A.data_ptr(), _ld(A), self.nb, self.linv_ptr,
+        trsm_chol_factor(self.n, _dev(A, torch.float64, "A"), _ld(A), self.nb, self.linv_ptr,
                          self.workspace_ptr, _stream_handle(torch, A.device))
 
     def linv_blocks(self):
@@ -548,10 +565,10 @@ class LU:
     def factor(self, A) -> None:
         """In place: A becomes L (strictly lower, unit diagonal implied) and U."""
         import torch
-        if A.dtype != torch.float64 or A.shape[0] != self.n or A.shape[1] < self.n:
+        if A.shape[0] != self.n or A.shape[1] < self.n:
             raise ValueError("A must be an n x n float64 tensor")
-        trsm_lu_factor(self.n, A.data_ptr(), _ld(A), self.nb, self.linv_ptr, self.uinv_ptr,
-                       self.workspace_ptr, _stream_handle(torch, A.device))
+        trsm_lu_factor(self.n, _dev(A, torch.float64, "A"), _ld(A), self.nb, self.linv_ptr,
+                       self.uinv_ptr, self.workspace_ptr, _stream_handle(torch, A.device))
 
     def _blocks(self, buf):
         import torch

@@ -273,3 +273,20 @@ def test_lu_sizes_and_validation_without_gpu(T):
     assert lib.trsm_lu_factor(64, fake, 63, 0, fake, fake, fake, None) == T.EINVAL
     assert lib.trsm_lu_factor(64, fake, 64, 0, fake, fake + 8, fake, None) == T.EINVAL
     assert lib.trsm_lu_factor(64, fake, 64, 0, fake, fake, fake + 8, None) == T.EINVAL
+
+
+def test_binding_refuses_host_tensors_and_overlapping_rows(T):
+    # a host tensor must never reach the library as a device pointer; the
+    # binding refuses it (and wrong element types, overlapping rows) first
+    import torch
+    A = torch.zeros((8, 8), dtype=torch.float64)
+    with pytest.raises(ValueError, match="CUDA"):
+        T.Cholesky(8, 0, device="cpu").factor(A)
+    with pytest.raises(ValueError, match="CUDA"):
+        T.LU(8, 0, device="cpu").factor(A)
+    with pytest.raises(ValueError, match="CUDA"):
+        T._dev(A, torch.float64, "L")
+    with pytest.raises(ValueError, match="overlap"):
+        T._ld(torch.zeros(64, dtype=torch.float64).as_strided((8, 8), (1, 1)))
+    assert T._ld(torch.zeros((5, 0))) == 1
+    assert T._ld(torch.zeros((3, 7))[:, :4]) == 7
