@@ -187,3 +187,43 @@ def test_empty(torch, T):
     Ad = torch.zeros((1, 1), dtype=torch.float64, device="cuda")
     T.trsm_lu_factor(0, Ad.data_ptr(), 1, 0, f.linv_ptr, f.uinv_ptr, f.workspace_ptr, 0)
     assert f.check() == (T.OK, -1)
+
+
+def test_concurrent_factorizations_on_two_streams(torch, T):
+    # two host threads, each with its own stream and buffers, share the
+    # library's side stream: both results must equal their lone results
+    import threading
+    n, nb = 1100, 128
+    mats = [gen.diag_dominant(n, 50 + t) for t in range(2)]
+    lone = []
+    for A in mats:
+        _, _, full, f = gpu_lu(torch, T, A, nb)
+        assert f.check() == (T.OK, -1)
+        lone.append(full)
+    out = [None, None]
+    errors = []
+
+    def work(t):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                Ad = torch.from_numpy(mats[t]).cuda()
+                f = T.LU(n, nb, device="cuda")
+                for _ in range(3):
+                    Ad.copy_(torch.from_numpy(mats[t]))
+                    T.trsm_lu_factor(n, Ad.data_ptr(), n, nb, f.linv_ptr, f.uinv_ptr,
+                                     f.workspace_ptr, s.cuda_stream)
+                s.synchronize()
+                assert f.check() == (T.OK, -1)
+                out[t] = Ad.cpu().numpy()
+        except Exception as e:   # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors
+    for t in range(2):
+        assert np.array_equal(out[t], lone[t])
