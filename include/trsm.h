@@ -70,6 +70,11 @@ typedef enum trsm_precision {
 #define TRSM_FLAG_TRANSPOSE   0x10u /* F64/F32: solve L^T X = B (the transposed problem, upper
                                        triangular, backward sweep) with the same L; with a
                                        forward plan this gives A^{-1} B for A = L L^T */
+#define TRSM_FLAG_UPPER       0x20u /* F64/F32: the matrix argument is an upper-triangular U
+                                       (row-major, only its upper triangle and diagonal are
+                                       read) and the plan solves U X = B by the backward sweep
+                                       with U's inverted diagonal blocks, e.g. the U of
+                                       trsm_lu_factor in place; not with TRSM_FLAG_TRANSPOSE */
 #define TRSM_FLAG_LARGE_TILES 0x8u  /* every product uses 128 x 128 tiles and an unsplit
                                        reduction (default: products with few tiles use 64 x 64
                                        tiles and split K); one of the tile policies
@@ -207,6 +212,11 @@ trsm_status trsm_plan_last_error(trsm_plan_t plan, trsm_status* status, int64_t*
  *  With TRSM_FLAG_TRANSPOSE the plan solves L^T X = B: trsm_invert_diag
  *  also stored U = L^T and the inverses of U's diagonal blocks in Linv
  *  (linv_bytes covers them), and the sweep runs from the last block up.
+ *  With TRSM_FLAG_UPPER the argument L is an upper-triangular U: both
+ *  trsm_invert_diag and trsm_solve read its upper triangle (zero or
+ *  non-finite diagonal entries give TRSM_ESINGULAR as for L), Linv holds the
+ *  inverses of U's diagonal blocks, and the sweep runs from the last block
+ *  up, reading U in place.
  */
 trsm_status trsm_solve(trsm_plan_t plan, const void* L, int64_t ldl, const void* Linv,
                        const void* B, int64_t ldb, void* X, int64_t ldx, void* workspace,

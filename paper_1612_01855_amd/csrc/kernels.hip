@@ -24,7 +24,7 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 1 << 20) {
 template <typename TL>
 __global__ void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl, int64_t n,
                                     int64_t n0, int64_t m, double* __restrict__ Linv,
-                                    unsigned long long* bad) {
+                                    unsigned long long* bad, bool upper) {
   const int64_t per = n0 * n0;
   const int64_t total = per * m;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -34,7 +34,7 @@ __global__ void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl, int64
     const int64_t gr = b * n0 + i, gc = b * n0 + j;
     double v;
     if (gr < n && gc < n) {
-      v = (j <= i) ? static_cast<double>(L[gr * ldl + gc]) : 0.0;
+      v = (j <= i) ? static_cast<double>(upper ? L[gc * ldl + gr] : L[gr * ldl + gc]) : 0.0;
       if (i == j && (!(v != 0.0) || !isfinite(v))) atomicMin(bad, (unsigned long long)gr);
     } else {
       v = (i == j) ? 1.0 : 0.0;
@@ -352,15 +352,16 @@ __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ p
 
 template <typename TL>
 hipError_t launch_extract_diag(const TL* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
-                               double* Linv, unsigned long long* bad, hipStream_t s) {
+                               double* Linv, unsigned long long* bad, hipStream_t s, bool upper) {
   if (m <= 0) return hipSuccess;
-  extract_diag_kernel<TL><<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(L, ldl, n, n0, m, Linv, bad);
+  extract_diag_kernel<TL><<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(L, ldl, n, n0, m, Linv, bad,
+                                                                      upper);
   return hipGetLastError();
 }
 template hipError_t launch_extract_diag<double>(const double*, int64_t, int64_t, int64_t, int64_t,
-                                                double*, unsigned long long*, hipStream_t);
+                                                double*, unsigned long long*, hipStream_t, bool);
 template hipError_t launch_extract_diag<float>(const float*, int64_t, int64_t, int64_t, int64_t,
-                                               double*, unsigned long long*, hipStream_t);
+                                               double*, unsigned long long*, hipStream_t, bool);
 
 hipError_t launch_trtri_leaf(double* Linv, int64_t n0, int64_t m, int64_t nb, hipStream_t s) {
   if (m <= 0) return hipSuccess;

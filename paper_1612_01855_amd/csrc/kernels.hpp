@@ -7,10 +7,14 @@ namespace trsm {
 
 // Copy the m diagonal n0 x n0 blocks of L (lower part, zeros above) into the
 // packed binary64 buffer Linv; positions past row/column n get the identity.
-// Records min(row) of any zero / non-finite diagonal entry in *bad.
+// Records min(row) of any zero / non-finite diagonal entry in *bad.  With
+// `upper`, L is an upper-triangular U and the blocks copied are U_bb^T (the
+// lower triangles of the transposed diagonal blocks; U below its diagonal is
+// not read).
 template <typename TL>
 hipError_t launch_extract_diag(const TL* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
-                               double* Linv, unsigned long long* bad, hipStream_t s);
+                               double* Linv, unsigned long long* bad, hipStream_t s,
+                               bool upper = false);
 
 // Invert, in place, every nb x nb diagonal leaf of every packed block
 // (nb <= 64): column-oriented substitution on the identity in LDS.

@@ -668,10 +668,14 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
   if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD |
-                TRSM_FLAG_LARGE_TILES | TRSM_FLAG_TRANSPOSE))
+                TRSM_FLAG_LARGE_TILES | TRSM_FLAG_TRANSPOSE | TRSM_FLAG_UPPER))
     return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_TRANSPOSE) &&
       (is_mixed(prec) || (flags & (TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD))))
+    return TRSM_EINVAL;
+  if ((flags & TRSM_FLAG_UPPER) &&
+      (is_mixed(prec) ||
+       (flags & (TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD | TRSM_FLAG_TRANSPOSE))))
     return TRSM_EINVAL;
   if (n * k > ((int64_t)1 << 31) - 1 || n * n > ((int64_t)1 << 31) * 8) return TRSM_EINVAL;
   trsm_plan_s* P = new (std::nothrow) trsm_plan_s();
@@ -722,6 +726,11 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     off = align_up(off + (size_t)n * P->ldu * es);
     P->off_uinv = off;
     off = align_up(off + (size_t)m * n0 * n0 * es);
+  }
+  if (flags & TRSM_FLAG_UPPER) {
+    // the inverses of U's diagonal blocks; U itself is read in place
+    P->off_uinv = off;
+    off = align_up(off + (size_t)m * n0 * n0 * elem_size(prec));
   }
   P->linv_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : off;
   // workspace
@@ -814,10 +823,13 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
   SplitScope split_scope(large ? nullptr : P->d_split,
                          (P->d_split && !large) ? (int64_t)P->inv_split_bytes : 0);
   TRSM_HIP(hipMemsetAsync(P->d_bad, 0xFF, sizeof(unsigned long long), s));
+  // an upper plan inverts the transposed blocks U_ii^T (lower) and
+  // transposes the inverses back below
+  const bool upper = P->flags & TRSM_FLAG_UPPER;
   if (P->prec == TRSM_F32)
-    TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s));
+    TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s, upper));
   else
-    TRSM_HIP(launch_extract_diag<double>((const double*)L, ldl, n, n0, m, L64, P->d_bad, s));
+    TRSM_HIP(launch_extract_diag<double>((const double*)L, ldl, n, n0, m, L64, P->d_bad, s, upper));
   TRSM_HIP(launch_trtri_leaf(L64, n0, m, P->leaf, s));
   if (P->leaf < n0) {
     TRSM_HIP(rec_tri_inv_levels(L64, n0, m, P->leaf, s));
@@ -840,6 +852,16 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
       TRSM_HIP((launch_transpose<double, double>(L64, n0, (double*)(base + P->off_uinv), n0, n0,
                                                  n0, m, n0 * n0, n0 * n0, false, s)));
     }
+  }
+  if (upper) {
+    // Uinv_ii = ((U_ii^T)^{-1})^T
+    if (P->prec == TRSM_F32)
+      TRSM_HIP((launch_transpose<float, float>((const float*)(base + P->off_linv32), n0,
+                                               (float*)(base + P->off_uinv), n0, n0, n0, m,
+                                               n0 * n0, n0 * n0, false, s)));
+    else
+      TRSM_HIP((launch_transpose<double, double>(L64, n0, (double*)(base + P->off_uinv), n0, n0,
+                                                 n0, m, n0 * n0, n0 * n0, false, s)));
   }
   if (is_mixed(P->prec)) {
     float* rs = (float*)(base + P->off_rscale);
@@ -912,6 +934,14 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
     }
     if (X != B) TRSM_HIP(launch_copy2d<float, float>((const float*)B, ldb, (float*)X, ldx, n, k, 1.0, s));
     return rec_solve<float>(n, k, (const float*)L, ldl, (float*)X, ldx, 64, s);
+  }
+  if (P->flags & TRSM_FLAG_UPPER) {
+    if (P->prec == TRSM_F64)
+      return sweep_back<double>(*P, (const double*)L, ldl, (const double*)(lb + P->off_uinv),
+                                (const double*)B, ldb, (double*)X, ldx, (double*)(ws + P->ws_r),
+                                s);
+    return sweep_back<float>(*P, (const float*)L, ldl, (const float*)(lb + P->off_uinv),
+                             (const float*)B, ldb, (float*)X, ldx, (float*)(ws + P->ws_r), s);
   }
   if (P->flags & TRSM_FLAG_TRANSPOSE) {
     if (P->prec == TRSM_F64)

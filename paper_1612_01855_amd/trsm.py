@@ -31,6 +31,7 @@ FLAG_RECURSIVE = 0x2
 FLAG_LOOKAHEAD = 0x4
 FLAG_LARGE_TILES = 0x8
 FLAG_TRANSPOSE = 0x10
+FLAG_UPPER = 0x20
 
 
 class PlanInfo(ctypes.Structure):
@@ -453,12 +454,15 @@ class Solver:
         trsm_invert_diag(self.plan, _dev(L, self._dtype(), "L"), _ld(L), self.linv_ptr,
                          _stream_handle(torch, L.device))
 
-    def solve(self, L, B, X=None, info: Optional[Info] = None) -> object:
+    def solve(self, L, B, X=None, info: Optional[Info] = None, linv_ptr: int = 0) -> object:
+        """X = L^{-1} B with this plan's inverted blocks (or, via linv_ptr,
+        blocks in the same layout made elsewhere, e.g. by a factorization)."""
         import torch
         if X is None:
             X = torch.empty_like(B)
         dt = self._dtype()
-        trsm_solve(self.plan, _dev(L, dt, "L"), _ld(L), self.linv_ptr, _dev(B, dt, "B"), _ld(B),
+        trsm_solve(self.plan, _dev(L, dt, "L"), _ld(L), linv_ptr or self.linv_ptr,
+                   _dev(B, dt, "B"), _ld(B),
                    _dev(X, dt, "X"), _ld(X), self.workspace_ptr,
                    _stream_handle(torch, B.device), info)
         return X
@@ -601,6 +605,32 @@ def lu_nopiv(A, nb: int = 0):
     L = torch.tril(F, -1)
     L.diagonal().fill_(1.0)
     return L, torch.triu(F)
+
+
+def lu_solve(A, B, nb: int = 0):
+    """X = A^{-1} B on the GPU (binary64) by the LU factorization without row
+    exchanges: L Y = B with the factorization's inverted blocks, then U X = Y
+    with an upper plan reading U in the factored copy of A.  Raises
+    TrsmError(ESINGULAR) at a zero or non-finite pivot."""
+    import torch
+    n, k = B.shape
+    F = A.clone()
+    f = LU(n, nb, device=A.device)
+    f.factor(F)
+    fwd = Solver.create(n, k, "f64", n0=f.nb, device=B.device)
+    up = Solver.create(n, k, "f64", 0, FLAG_UPPER, device=B.device)
+    try:
+        Y = fwd.solve(F, B.contiguous(), linv_ptr=f.linv_ptr)
+        up.invert(F)
+        X = up.solve(F, Y)
+        st, idx = f.check()
+        if st != OK:
+            raise TrsmError(st, f"lu_solve (row {idx})")
+        return X
+    finally:
+        torch.cuda.current_stream(B.device).synchronize()
+        fwd.close()
+        up.close()
 
 
 def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None):

@@ -43,7 +43,7 @@ def test_status_strings(T):
 
 
 @pytest.mark.parametrize("args", [(-1, 4, 0, 0, 0), (4, -1, 0, 0, 0), (8, 8, 9, 0, 0),
-                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x20),
+                                  (8, 8, 0, 3, 0), (8, 8, 0, -2, 0), (8, 8, 0, 0, 0x80), (8, 8, 0, 0, 0x40),
                                   (8, 8, 2, 0, 2),
                                   # beyond the addressable sizes: n k > 2^31 - 1, n > 2^30
                                   (65536, 32769, 0, 0, 0), ((1 << 30) + 1, 1, 0, 0, 0),
@@ -215,6 +215,28 @@ def test_transposed_plans(T):
     for prec, flags in [(T.MIXED_BF16, T.FLAG_TRANSPOSE),
                         (T.F64, T.FLAG_TRANSPOSE | T.FLAG_RECURSIVE),
                         (T.F64, T.FLAG_TRANSPOSE | T.FLAG_LOOKAHEAD)]:
+        with pytest.raises(T.TrsmError):
+            T.trsm_plan(300, 20, prec, 64, flags)
+
+
+def test_upper_plans(T):
+    p0 = T.trsm_plan(300, 20, T.F64, 64, 0)
+    p1 = T.trsm_plan(300, 20, T.F64, 64, T.FLAG_UPPER)
+    p2 = T.trsm_plan(300, 20, T.F32, 64, T.FLAG_UPPER)
+    try:
+        a, b, c = (T.trsm_plan_get_info(p) for p in (p0, p1, p2))
+        # U is read in place: only the inverses of its five diagonal blocks are added
+        assert b.linv_bytes >= a.linv_bytes + 5 * 64 * 64 * 8
+        assert b.linv_bytes < a.linv_bytes + 300 * 300 * 8
+        assert b.workspace_bytes == a.workspace_bytes
+        assert c.linv_bytes > 0 and b.flags & T.FLAG_UPPER
+    finally:
+        for p in (p0, p1, p2):
+            T.trsm_plan_destroy(p)
+    for prec, flags in [(T.MIXED_BF16, T.FLAG_UPPER), (T.MIXED_FP8, T.FLAG_UPPER),
+                        (T.F64, T.FLAG_UPPER | T.FLAG_TRANSPOSE),
+                        (T.F64, T.FLAG_UPPER | T.FLAG_RECURSIVE),
+                        (T.F64, T.FLAG_UPPER | T.FLAG_LOOKAHEAD)]:
         with pytest.raises(T.TrsmError):
             T.trsm_plan(300, 20, prec, 64, flags)
 
