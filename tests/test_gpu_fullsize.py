@@ -214,6 +214,22 @@ def test_transposed_f64_n16384_k16384(torch, T):
     assert err <= TOL64
 
 
+def test_upper_f64_n16384_k16384(torch, T):
+    # U = L^T given as an upper-triangular matrix (NaN below the diagonal)
+    n = k = 16384
+    L, B = gen.easy_system(n, k, 8)
+    U = np.ascontiguousarray(L.T)
+    U[np.tril_indices(n, -1)] = np.nan
+    cols = sample_cols(k, 108)
+    Xs, X = gpu_solve_cols(torch, T, torch.from_numpy(U).cuda(), torch.from_numpy(B).cuda(),
+                           "f64", n0=2048, flags=T.FLAG_UPPER, cols=cols)
+    del X, U
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle.trsm_t(L, np.ascontiguousarray(B[:, cols])))
+    log(f"full size upper f64: sampled rel err {err:.2e}")
+    assert err <= TOL64
+
+
 @pytest.mark.parametrize("ratio", [None, 1e-12])
 def test_cholesky_factor_n16384(torch, T, ratio):
     """The blocked Cholesky factorization at n = 16384 in the benchmark's
