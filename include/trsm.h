@@ -74,7 +74,9 @@ typedef enum trsm_precision {
                                        (row-major, only its upper triangle and diagonal are
                                        read) and the plan solves U X = B by the backward sweep
                                        with U's inverted diagonal blocks, e.g. the U of
-                                       trsm_lu_factor in place; not with TRSM_FLAG_TRANSPOSE */
+                                       trsm_lu_factor in place; not with the mixed precisions
+                                       nor with TRSM_FLAG_TRANSPOSE, TRSM_FLAG_RECURSIVE or
+                                       TRSM_FLAG_LOOKAHEAD (trsm_plan: TRSM_EINVAL) */
 #define TRSM_FLAG_LARGE_TILES 0x8u  /* every product uses 128 x 128 tiles and an unsplit
                                        reduction (default: products with few tiles use 64 x 64
                                        tiles and split K); one of the tile policies
