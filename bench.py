@@ -372,20 +372,25 @@ def run_suite(args, torch, T, gen, dev):
     del L64
     torch.cuda.empty_cache()
 
-    # the transposed problem L^T X = B (backward sweep over U = L^T), invert + solve
+    # the transposed problem L^T X = B (backward sweep over U = L^T), and the
+    # upper problem U X = B with U = L^T given as an upper-triangular matrix
+    # (read in place), invert + solve
+    problems = ((0, "L X = B"), (T.FLAG_TRANSPOSE, "L^T X = B"),
+                (T.FLAG_UPPER, "U X = B (U = L^T stored)"))
     for (n, k, prec) in ((16384, 16384, "f64"), (8192, 8192, "f64"), (8192, 8192, "f32")):
         L, B = gen.easy_system(n, k, args.seed)
         L64 = torch.from_numpy(L).to(dev)
         B64 = torch.from_numpy(B).to(dev)
         del L, B
-        for flags in (0, T.FLAG_TRANSPOSE):
-            ms, info, _ = time_solves(T, torch, dev, L64, B64, prec, 2048, flags, 3)
+        for flags, problem in problems:
+            M = L64.t().contiguous() if flags == T.FLAG_UPPER else L64
+            ms, info, _ = time_solves(T, torch, dev, M, B64, prec, 2048, flags, 3)
+            del M
             tf = float(n) * n * k / (ms * 1e-3) / 1e12
             emit({"suite": "transposed", "n": n, "k": k, "precision": prec, "n0": int(info.n0),
-                  "problem": "L^T X = B" if flags else "L X = B", "ms": round(ms, 3),
+                  "problem": problem, "ms": round(ms, 3),
                   "tflops_n2k": round(tf, 2), "frac_peak": round(tf / PEAK[prec], 4)})
-            log(f"suite {'transposed' if flags else 'forward'} {prec} n=k={n}: {ms:.2f} ms "
-                f"{tf:.2f} TF")
+            log(f"suite {problem} {prec} n=k={n}: {ms:.2f} ms {tf:.2f} TF")
         del L64, B64
         torch.cuda.empty_cache()
 
