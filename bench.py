@@ -233,7 +233,7 @@ def cholesky_bench(args, torch, T, gen, dev, emit):
     solve: median of 3 timed factorizations after a warm one, flops n^3 / 3,
     and the backward error ||A - L L^T|| / ||A|| on 64 sampled rows."""
     sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
-    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512, 1024)
+    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 128, 256, 512, 1024)
     for n in sizes:
         A0 = gen.spd_on(torch, dev, n, args.seed)
         for nb in blocks:
@@ -275,7 +275,7 @@ def lu_bench(args, torch, T, gen, dev, emit):
     one, flops 2 n^3 / 3, backward error ||A - L U|| / ||A|| on 64 sampled
     rows."""
     sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
-    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512)
+    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 128, 256, 512)
     for n in sizes:
         A0 = gen.diag_dominant_on(torch, dev, n, args.seed)
         for nb in blocks:

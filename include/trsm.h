@@ -385,10 +385,10 @@ trsm_status trsm_server_destroy(trsm_server_t srv);
  * rows); then A(T_j, T_j) -= L(T_j, S_j) L(T_j, S_j)^T on the lower triangle.
  *
  * trsm_chol_sizes(n, nb, &nb_used, &linv_bytes, &workspace_bytes): host only.
- *  nb = 0 picks 512 for n >= 12288 and 256 below (the faster of the two as
- *  measured), at most the next power of two >= max(n, 64); otherwise nb
- *  must be a power of two in [64, 4096].  TRSM_EINVAL for n < 0, n > 2^20 or
- *  a bad nb.  Any output pointer may be NULL.
+ *  nb = 0 picks 512 for n >= 12288, 256 for 6144 <= n < 12288 and 128 below
+ *  (the fastest as measured), at most the next power of two >= max(n, 64);
+ *  otherwise nb must be a power of two in [64, 4096].  TRSM_EINVAL for
+ *  n < 0, n > 2^20 or a bad nb.  Any output pointer may be NULL.
  * trsm_chol_factor(n, A, lda, nb, Linv, workspace, stream): A is a device
  *  binary64 row-major n x n matrix (lda >= n) of which only the lower
  *  triangle (diagonal included) is read; on return its lower triangle holds

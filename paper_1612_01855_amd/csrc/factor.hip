@@ -41,6 +41,7 @@ namespace {
 constexpr int kLeaf = 64;
 constexpr int64_t kDefaultNb = 512;
 constexpr int64_t kLargeN = 12288;
+constexpr int64_t kMidN = 6144;
 constexpr int64_t kMaxNb = 4096;
 constexpr size_t kCholSplitBytes = (size_t)32 << 20;
 constexpr size_t kAl = 256;
@@ -683,10 +684,12 @@ struct Sizes {
 
 trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z, bool lu = false) {
   if (n < 0 || nb < 0) return TRSM_EINVAL;
-  // measured: 256-row blocks are faster up to n = 8192, 512-row ones at 16384
+  // measured: 128-row blocks are the fastest up to n = 4096, 256-row ones at
+  // 8192 and 512-row ones at 16384
   if (nb == 0)
-    nb = std::min<int64_t>(n >= kLargeN ? kDefaultNb : kDefaultNb / 2,
-                           pow2_at_least(std::max<int64_t>(n, kLeaf)));
+    nb = std::min<int64_t>(
+        n >= kLargeN ? kDefaultNb : (n >= kMidN ? kDefaultNb / 2 : kDefaultNb / 4),
+        pow2_at_least(std::max<int64_t>(n, kLeaf)));
   if (nb < kLeaf || nb > kMaxNb || (nb & (nb - 1))) return TRSM_EINVAL;
   if (n > (int64_t)1 << 20) return TRSM_EINVAL;
   const int64_t m = n > 0 ? (n + nb - 1) / nb : 0;

@@ -245,6 +245,9 @@ def test_cholesky_sizes_and_validation_without_gpu(T):
     # default block: 512 from n = 12288 on, 256 below, at most pow2 >= max(n, 64)
     assert T.trsm_chol_sizes(10)[0] == 64
     assert T.trsm_chol_sizes(100)[0] == 128
+    assert T.trsm_chol_sizes(4096)[0] == 128
+    assert T.trsm_chol_sizes(6144)[0] == 256
+    assert T.trsm_lu_sizes(4096)[0] == 128
     assert T.trsm_chol_sizes(8192)[0] == 256
     assert T.trsm_chol_sizes(16384)[0] == 512
     nb, lb, wb = T.trsm_chol_sizes(1000, 128)
