@@ -75,26 +75,31 @@ def _load():
             return _lib
         if not os.path.exists(_SO):
             build(force=False)
-        lib = ctypes.CDLL(_SO)
-        i64, dp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
-        for name in ("oracle_trsm_f64", "oracle_trsm_q", "oracle_trsm_t_f64"):
-            f = getattr(lib, name)
-            f.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, ci]
-            f.restype = ci
-        lib.oracle_residual_f64.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ci]
-        lib.oracle_residual_f64.restype = ci
-        lib.oracle_fro_lower.argtypes = [i64, dp, i64]
-        lib.oracle_fro_lower.restype = ctypes.c_double
-        lib.oracle_fro_dense.argtypes = [i64, i64, dp, i64]
-        lib.oracle_fro_dense.restype = ctypes.c_double
-        lib.oracle_chol_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
-        lib.oracle_chol_f64.restype = ci
-        lib.oracle_lu_nopiv_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
-        lib.oracle_lu_nopiv_f64.restype = ci
-        lib.oracle_max_threads.argtypes = []
-        lib.oracle_max_threads.restype = ci
-        _lib = lib
-        return lib
+        _lib = bind(ctypes.CDLL(_SO))
+        return _lib
+
+
+def bind(lib):
+    """Declare the argument and result types of the library's functions (also
+    used on copies compiled from planted-mistake sources in the tests)."""
+    i64, dp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    for name in ("oracle_trsm_f64", "oracle_trsm_q", "oracle_trsm_t_f64"):
+        f = getattr(lib, name)
+        f.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, ci]
+        f.restype = ci
+    lib.oracle_residual_f64.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ci]
+    lib.oracle_residual_f64.restype = ci
+    lib.oracle_fro_lower.argtypes = [i64, dp, i64]
+    lib.oracle_fro_lower.restype = ctypes.c_double
+    lib.oracle_fro_dense.argtypes = [i64, i64, dp, i64]
+    lib.oracle_fro_dense.restype = ctypes.c_double
+    lib.oracle_chol_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
+    lib.oracle_chol_f64.restype = ci
+    lib.oracle_lu_nopiv_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
+    lib.oracle_lu_nopiv_f64.restype = ci
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = ci
+    return lib
 
 
 def _rows(a: np.ndarray) -> np.ndarray:

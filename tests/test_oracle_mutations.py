@@ -16,6 +16,7 @@ import pytest
 import oracle
 from oracle import exact
 from paper_1612_01855_amd import inputs as gen
+from norm_pins import failed_norm_pins
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
 
@@ -30,6 +31,27 @@ MUTANTS = {
     "multiply_not_divide": ("xi[c] = xi[c] / d;", "xi[c] = xi[c] * d;"),
     "wrong_diagonal": ("const double d = li[i];", "const double d = L[i * ldl + (i ? i - 1 : 0)];"),
     "rhs_wrong_column": ("xi[c] = bi[c];", "xi[c] = bi[c0];"),
+}
+
+
+# Planted mistakes in the Frobenius norms every tolerance goes through.
+NORM_MUTANTS = {
+    "lower_no_sqrt": ("for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);\n  return (double)r;\n}\n\ndouble oracle_fro_dense",
+                      "for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);\n  return (double)s;\n}\n\ndouble oracle_fro_dense"),
+    "dense_no_sqrt": ("for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);\n  return (double)r;\n}\n\n/* Cholesky",
+                      "for (int it = 0; it < 3; ++it) r = 0.5Q * (r + s / r);\n  return (double)s;\n}\n\n/* Cholesky"),
+    "lower_drops_diagonal": ("for (int64_t j = 0; j <= i; ++j) {\n      __float128 v = (__float128)L[i * ldl + j];",
+                             "for (int64_t j = 0; j < i; ++j) {\n      __float128 v = (__float128)L[i * ldl + j];"),
+    "lower_reads_upper": ("__float128 v = (__float128)L[i * ldl + j];",
+                          "__float128 v = (__float128)L[j * ldl + i];"),
+    "lower_wrong_leading_dim": ("__float128 v = (__float128)L[i * ldl + j];",
+                                "__float128 v = (__float128)L[i * n + j];"),
+    "dense_wrong_leading_dim": ("__float128 v = (__float128)A[i * lda + c];",
+                                "__float128 v = (__float128)A[i * k + c];"),
+    "dense_drops_last_column": ("for (int64_t c = 0; c < k; ++c) {\n      __float128 v = (__float128)A[i * lda + c];",
+                                "for (int64_t c = 0; c + 1 < k; ++c) {\n      __float128 v = (__float128)A[i * lda + c];"),
+    "lower_sum_not_squared": ("      s += v * v;\n    }\n  /* square root",
+                              "      s += v < 0 ? -v : v;\n    }\n  /* square root"),
 }
 
 
@@ -104,3 +126,18 @@ def test_mutant_is_caught(name, tmp_path):
     mutated = SRC.replace(old, new, 1)
     failed = _failed_pins(_solver(_compile(mutated, tmp_path)))
     assert failed, f"mutant {name} passed every pin"
+
+
+def test_unmodified_source_passes_norm_pins(tmp_path, monkeypatch):
+    monkeypatch.setattr(oracle, "_lib", oracle.bind(_compile(SRC, tmp_path)))
+    assert failed_norm_pins(oracle) == []
+
+
+@pytest.mark.parametrize("name", sorted(NORM_MUTANTS))
+def test_norm_mutant_is_caught(name, tmp_path, monkeypatch):
+    old, new = NORM_MUTANTS[name]
+    assert SRC.count(old) == 1, "mutation anchor not found once in oracle.c"
+    lib = oracle.bind(_compile(SRC.replace(old, new, 1), tmp_path))
+    monkeypatch.setattr(oracle, "_lib", lib)
+    failed = failed_norm_pins(oracle)
+    assert failed, f"norm mutant {name} passed every pin"
