@@ -142,6 +142,28 @@ __global__ __launch_bounds__(256) void lowcopy_kernel(const double* __restrict__
   if (lane == 0) rscale[r * m + c] = ldexpf(1.0f, -e);
 }
 
+// out[r * cols + c] = low(a[r * cols + c] 2^e_r) with one power-of-two scale
+// per row (its largest magnitude placed just below `target`) and
+// rs[r] = 2^-e_r; one wave per row.
+template <typename TO>
+__global__ __launch_bounds__(256) void rowscale_copy_kernel(const double* __restrict__ a,
+                                                            int64_t rows, int64_t cols,
+                                                            TO* __restrict__ out,
+                                                            float* __restrict__ rs, float target) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (r >= rows) return;
+  const double* src = a + r * cols;
+  double mx = 0.0;
+  for (int64_t j = lane; j < cols; j += 64) mx = fmax(mx, fabs(src[j]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  int e = 0;
+  if (mx > 0.0) e = ilogb((double)target) - ilogb(mx) - 1;
+  for (int64_t j = lane; j < cols; j += 64) out[r * cols + j] = cvt<TO>(ldexp(src[j], e));
+  if (lane == 0) rs[r] = ldexpf(1.0f, -e);
+}
+
 // Largest |D| over a rows x cols block as float bits: the bit patterns of
 // non-negative floats order like their values (and a NaN orders above
 // infinity, so it is not lost).  out[0] must start at zero.
@@ -150,12 +172,9 @@ __global__ __launch_bounds__(256) void absmax_bits_kernel(const float* __restric
                                                           unsigned* __restrict__ out) {
   __shared__ unsigned wmax[4];
   unsigned mx = 0;
-  const int64_t total = rows * cols;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / cols, c = e - r * cols;
-    mx = max(mx, __float_as_uint(D[r * ldd + c]) & 0x7FFFFFFFu);
-  }
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
+    for (int64_t c = threadIdx.x; c < cols; c += blockDim.x)
+      mx = max(mx, __float_as_uint(D[r * ldd + c]) & 0x7FFFFFFFu);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (unsigned)__shfl_xor((int)mx, off));
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
@@ -419,6 +438,19 @@ hipError_t launch_lowcopy(const double* L, int64_t ldl, int64_t n, int64_t n0, i
                                                                           rscale, target);
   return hipGetLastError();
 }
+template <typename TO>
+hipError_t launch_rowscale_copy(const double* a, int64_t rows, int64_t cols, TO* out, float* rs,
+                               float target, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  rowscale_copy_kernel<TO><<<grid_for(rows * 64, 256, INT64_MAX), 256, 0, s>>>(a, rows, cols, out,
+                                                                              rs, target);
+  return hipGetLastError();
+}
+template hipError_t launch_rowscale_copy<bf16_t>(const double*, int64_t, int64_t, bf16_t*, float*,
+                                                 float, hipStream_t);
+template hipError_t launch_rowscale_copy<f16_t>(const double*, int64_t, int64_t, f16_t*, float*,
+                                                float, hipStream_t);
+
 template hipError_t launch_lowcopy<bf16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
                                            bf16_t*, float*, float, hipStream_t);
 template hipError_t launch_lowcopy<f16_t>(const double*, int64_t, int64_t, int64_t, int64_t,
@@ -436,7 +468,7 @@ template <typename TO>
 hipError_t launch_lowx(const float* D, int64_t ldd, int64_t rows, int64_t cols, TO* XT,
                        int64_t ldx, unsigned* amax, float* xinv, int etarget, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  absmax_bits_kernel<<<grid_for(rows * cols, 256, 2048), 256, 0, s>>>(D, ldd, rows, cols, amax);
+  absmax_bits_kernel<<<(unsigned)std::min<int64_t>(rows, 2048), 256, 0, s>>>(D, ldd, rows, cols, amax);
   const int64_t tiles = ceil_div(rows, 64) * ceil_div(cols, 64);
   lowx_kernel<TO><<<(unsigned)tiles, 256, 0, s>>>(D, ldd, rows, cols, XT, ldx, amax, xinv, etarget);
   return hipGetLastError();

@@ -47,6 +47,12 @@ template <typename TO>
 hipError_t launch_lowcopy(const double* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
                           TO* Llow, float* rscale, float target, hipStream_t s);
 
+// out[r * cols + c] = low(a[r * cols + c] 2^e_r), one power-of-two scale per
+// row placing its largest magnitude just below `target`; rs[r] = 2^-e_r.
+template <typename TO>
+hipError_t launch_rowscale_copy(const double* a, int64_t rows, int64_t cols, TO* out, float* rs,
+                               float target, hipStream_t s);
+
 // Low-precision, transposed copy of a solved block of X with a power-of-two
 // scale taken from the block's largest magnitude (found on the device):
 // XT[c*ldx + r] = low(2^e * D[r*ldd + c]), 2^e placing the largest magnitude

@@ -20,9 +20,11 @@
 #include <vector>
 
 #include "common.hpp"
+#include "crt.hpp"
 #include "gemm.hpp"
-#include "tune.hpp"
 #include "kernels.hpp"
+#include "lpgemm.hpp"
+#include "tune.hpp"
 
 using namespace trsm;
 
@@ -200,6 +202,17 @@ struct trsm_plan_s {
   size_t ws_r = 0, ws_r64 = 0, ws_rl = 0, ws_d = 0, ws_xlow = 0, ws_xsc = 0, ws_part = 0,
          ws_norm = 0;
   size_t ws_split = 0, ws_split_bytes = 0;
+  // mixed plans: residue planes of L's strictly lower part (Linv buffer) and
+  // of the correction pieces and the products (workspace); npad = n rounded
+  // up to 64, ldz = k rounded up to 16
+  size_t off_crt_e = 0, off_crt_rowmax = 0, off_crt_rowpart = 0, off_crt_stats = 0,
+         off_crt_a = 0, off_crt_sl = 0;
+  // mixed plans: 16-bit copy of the inverted blocks with one scale per row
+  // (the diagonal apply of the first, coarse sweep)
+  size_t off_linv16 = 0, off_linv16_rs = 0;
+  size_t ws_q = 0, ws_z = 0, ws_colmax = 0, ws_ty = 0, ws_rpart = 0, ws_dpart = 0;
+  size_t ws_d1 = 0, ws_d2 = 0;   // the second and third correction pieces
+  int64_t npad = 0, ldz = 0;
   size_t ws_bytes = 0;
   unsigned long long* d_bad = nullptr;   // first singular row (device word)
   void* d_split = nullptr;               // split-K scratch of the inversion
@@ -491,18 +504,100 @@ trsm_status rec_solve(int64_t n, int64_t k, const T* L, int64_t ldl, T* X, int64
 // accumulation and per-(row, block) power-of-two scales), binary64 residual,
 // iterative refinement.
 // ---------------------------------------------------------------------------
+// Left-looking form for the 16-bit matrix cores: block i's right-hand side
+// is updated once, by all solved blocks at the same time,
+//   Rl(S_i) -= L(S_i, 0:i n0) X(0:i n0)
+// (one product with K = i n0, each block j of K carrying its own scales, see
+// LP_SEGMENTS), then X(S_i) = Linv32_ii Rl(S_i).  Same arithmetic per term
+// as the right-looking sweep, but the binary32 right-hand side is read and
+// written once per block instead of once per step.
+template <typename TL>
+bool low_sweep_left_ok(const trsm_plan_s& P, const TL* Llow, const TL* XlowT) {
+  if constexpr (std::is_same<TL, fp8_t>::value) {
+    return false;
+  } else {
+    lp::LpParams q = lp::lp_params();
+    q.A = Llow; q.lda = P.n;
+    q.B = XlowT; q.ldb = P.n;
+    q.K = (int)P.n0;
+    return P.n % 8 == 0 && P.n0 >= 64 && P.n0 % 64 == 0 && lp::lp_ok<TL>(q);
+  }
+}
+
+template <typename TL>
+trsm_status low_sweep_left(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
+                           const float* rscale, float* Rl, float* D, TL* XlowT, unsigned* amax,
+                           float* xinv, int etarget, const TL* Linv16, const float* linv16_rs,
+                           hipStream_t s) {
+  const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
+  unsigned* tamax = amax + 2 * m;          // scales of the coarse sweep's right-hand sides
+  float* tinv = (float*)(amax + 3 * m);
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
+    if (i > 0) {
+      lp::LpParams q = lp::lp_params();
+      q.A = Llow + r0 * n; q.lda = n;
+      q.B = XlowT; q.ldb = n;
+      q.Cin = Rl + r0 * k; q.ldci = k;
+      q.Cout = Rl + r0 * k; q.ldco = k;
+      q.rscale = rscale + r0 * m; q.ld_rs = m;
+      q.sscale = xinv;
+      q.seg_chunks = (int)(n0 * (int64_t)sizeof(TL) / lp::kChunk);
+      q.M = (int)sz; q.N = (int)k; q.K = (int)r0;
+      q.alpha = -1.0f; q.beta = 1.0f;
+      q.flags = lp::LP_BETA | lp::LP_SEGMENTS;
+      TRSM_HIP(timed(2.0 * sz * k * r0, s, [&] { return lp::launch_lp_gemm<TL, lp::EPI_F32>(q, 1, s); }));
+    }
+    if (Linv16) {
+      // coarse: X(S_i) = Linv_ii B'(S_i) on the 16-bit matrix cores, B'(S_i)
+      // rounded with one scale (its columns of XlowT are free until X(S_i)
+      // takes them)
+      TRSM_HIP(launch_lowx<TL>(Rl + r0 * k, k, sz, k, XlowT + r0, n, tamax + i, tinv + i, etarget, s));
+      lp::LpParams q = lp::lp_params();
+      q.A = Linv16 + i * n0 * n0; q.lda = n0;
+      q.B = XlowT + r0; q.ldb = n;
+      q.Cout = D + r0 * k; q.ldco = k;
+      q.rscale = linv16_rs + i * n0; q.ld_rs = 1;
+      q.ascale = tinv + i;
+      q.M = (int)sz; q.N = (int)k; q.K = (int)sz;
+      q.flags = lp::LP_ROWSCALE | lp::LP_A_LOWER;
+      TRSM_HIP(timed(1.0 * sz * sz * k, s, [&] { return lp::launch_lp_gemm<TL, lp::EPI_F32>(q, 1, s); }));
+    } else {
+      auto p = gemm_params<float, float, float, float>();
+      p.A = Linv32 + i * n0 * n0; p.lda = n0;
+      p.B = Rl + r0 * k; p.ldb = k;
+      p.Cout = D + r0 * k; p.ldco = k;
+      p.M = (int)sz; p.N = (int)k; p.K = (int)sz;
+      p.flags = G_A_LOWER | G_A_ZERO_UPPER;
+      use_split(p);
+      TRSM_HIP(timed(gemm_flops(p, 1), s, [&] {
+        return launch_gemm<float, float, float, float, 128, 128, 2, 2, false>(p, 1, s);
+      }));
+    }
+    if (i + 1 < m)
+      TRSM_HIP(launch_lowx<TL>(D + r0 * k, k, sz, k, XlowT + r0, n, amax + i, xinv + i, etarget, s));
+  }
+  return TRSM_OK;
+}
+
 template <typename TL>
 trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
                       const float* rscale, const double* rhs, int64_t ldr, double scale, float* Rl,
-                      float* D, TL* XlowT, unsigned* amax, float* xinv, hipStream_t s) {
+                      float* D, TL* XlowT, unsigned* amax, float* xinv, hipStream_t s,
+                      const TL* Linv16 = nullptr, const float* linv16_rs = nullptr) {
   const int64_t n = P.n, k = P.k, n0 = P.n0, m = P.m;
   // largest magnitude of a solved block -> [2^etarget, 2^(etarget+1)) in the
   // low copy: half keeps headroom below its largest finite value (65504)
   // (e4m3's largest finite value is 448 or 240 depending on the encoding:
   // keep the block maximum below 128)
   const int etarget = std::is_same<TL, f16_t>::value ? 14 : std::is_same<TL, fp8_t>::value ? 6 : 0;
-  TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
-  TRSM_HIP(launch_fill_u32(amax, m, 0u, s));
+  if (rhs) TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
+  TRSM_HIP(launch_fill_u32(amax, 4 * m, 0u, s));
+  if constexpr (!std::is_same<TL, fp8_t>::value) {
+    if (low_sweep_left_ok<TL>(P, Llow, XlowT))
+      return low_sweep_left<TL>(P, Linv32, Llow, rscale, Rl, D, XlowT, amax, xinv, etarget,
+                                Linv16, linv16_rs, s);
+  }
   for (int64_t i = 0; i < m; ++i) {
     const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
     // D(S_i) = Linv32_ii * Rl(S_i)
@@ -523,6 +618,24 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
       TRSM_HIP(launch_lowx<TL>(D + r0 * k, k, sz, k, XlowT + r0, n, amax + i, xinv + i, etarget,
                                s));
       const int64_t t0 = r0 + n0, rows = n - t0;
+      if constexpr (!std::is_same<TL, fp8_t>::value) {
+        lp::LpParams q = lp::lp_params();
+        q.A = Llow + t0 * n + r0; q.lda = n;
+        q.B = XlowT + r0; q.ldb = n;          // stored k x n: column c of X is a row
+        q.Cin = Rl + t0 * k; q.ldci = k;
+        q.Cout = Rl + t0 * k; q.ldco = k;
+        q.rscale = rscale + t0 * m + i; q.ld_rs = m;
+        q.ascale = xinv + i;                  // undo the block's scale
+        q.M = (int)rows; q.N = (int)k; q.K = (int)sz;
+        q.alpha = -1.0f; q.beta = 1.0f;
+        q.flags = lp::LP_BETA | lp::LP_ROWSCALE;
+        if (lp::lp_ok<TL>(q)) {
+          TRSM_HIP(timed(2.0 * rows * k * sz, s, [&] {
+            return lp::launch_lp_gemm<TL, lp::EPI_F32>(q, 1, s);
+          }));
+          continue;
+        }
+      }
       auto p = gemm_params<TL, float, float, float>();
       p.A = Llow + t0 * n + r0; p.lda = n;
       p.B = XlowT + r0; p.ldb = n;            // stored k x n: column c of X is a row
@@ -547,6 +660,62 @@ double pow2_scale_for(double maxabs) {
   return ldexp(1.0, -ilogb(maxabs));
 }
 
+// One refinement residual: the correction piece D (binary32; the correction
+// it stands for is D 2^yshift) is rounded in place to b bits per column, its
+// residues are multiplied with L's residue planes on the int8 matrix cores (P
+// moduli), and the recombination updates R (binary64, in the workspace) and
+// its binary32 copy, and X according to xmode (0: untouched, 1: X = piece,
+// 2: X += piece).  The norms land in the workspace (crt::launch_recombine).
+trsm_status crt_residual(const trsm_plan_s& P, const double* L, int64_t ldl, const char* lbuf,
+                         float* D, int yshift, int b, int nmod, const double* Rin, int64_t ldri,
+                         double* X, int64_t ldx, int xmode, char* ws, hipStream_t s) {
+  const int64_t n = P.n, k = P.k, npad = P.npad, ldz = P.ldz;
+  const crt::Table t = crt::make_table(nmod);
+  unsigned* colmax = (unsigned*)(ws + P.ws_colmax);
+  int* ty = (int*)(ws + P.ws_ty);
+  int8_t* Q = (int8_t*)(ws + P.ws_q);
+  int8_t* Z = (int8_t*)(ws + P.ws_z);
+  double* R64 = (double*)(ws + P.ws_r64);
+  TRSM_HIP(crt::launch_y_residues(D, k, n, npad, k, colmax, b, t, Q, npad, k * npad, ty, s));
+  lp::LpParams q = lp::lp_params();
+  q.A = lbuf + P.off_crt_e; q.lda = npad; q.sa = npad * npad;
+  q.B = Q; q.ldb = npad; q.sb = k * npad;
+  q.Z = Z; q.ldz = ldz; q.sz = npad * ldz;
+  q.M = (int)npad; q.N = (int)k; q.K = (int)npad;
+  q.flags = lp::LP_A_LOWER;
+  for (int p = 0; p < nmod; ++p) q.modulus[p] = t.mod[p];
+  TRSM_HIP(timed(1.0 * npad * npad * k * nmod, s, [&] {
+    return lp::launch_lp_gemm<int8_t, lp::EPI_MOD>(q, nmod, s);
+  }));
+  double* rpart = (double*)(ws + P.ws_rpart);
+  TRSM_HIP(crt::launch_recombine(Z, ldz, npad * ldz, t, (const int*)(lbuf + P.off_crt_sl), ty, D,
+                                 k, yshift, L, ldl, Rin, ldri, R64, k, (float*)(ws + P.ws_rl), X,
+                                 ldx, xmode, n, k, rpart, rpart + 4 * crt::kRecBlocks, s));
+  return TRSM_OK;
+}
+
+// Moduli for a product of an a-bit L with b-bit pieces (|C| < n 2^(a+b), and
+// M > 4 |C|), and the largest b those moduli allow.
+int crt_moduli(int a, int bmin, int64_t n, int* b_out) {
+  const int lgn = (int)ceil(log2((double)std::max<int64_t>(n, 2)));
+  const int P = crt::moduli_for_bits((double)(a + bmin + lgn + 2));
+  if (P < 0) return -1;
+  const crt::Table t = crt::make_table(P);
+  // pieces are rounded in binary32 (exact up to 24 bits)
+  *b_out = std::min((int)floor(t.log2M) - a - lgn - 2, 24);
+  return P;
+}
+
+// Iterative refinement with exact residuals.  Each correction D_j of the
+// low-precision sweep is rounded to b_j bits per column before it is added, so
+// that L times the accumulated X is an exact integer product (crt_residual):
+// the residual R_{j+1} = R_j - L D_j is then exact for the L whose strictly
+// lower part is rounded to a bits (relative to each row's largest entry), and
+// binary64 work is limited to one rounding per element.  The first piece is
+// rounded coarsely (about 8 bits: the next correction removes that error as
+// well), later ones to 20+ bits.  Stop when the next correction predicted from
+// the observed contraction, ||D_j|| * (||D_j|| / ||D_{j-1}||), falls below
+// 1e-14 ||X||, or a correction falls below 1e-15 ||X||; at most 10 corrections.
 template <typename TL>
 trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, const char* lbuf,
                         const double* B, int64_t ldb, double* X, int64_t ldx, char* ws,
@@ -555,7 +724,6 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   const float* Linv32 = (const float*)(lbuf + P.off_linv32);
   const TL* Llow = (const TL*)(lbuf + P.off_llow);
   const float* rscale = (const float*)(lbuf + P.off_rscale);
-  const double* d_lnorm = (const double*)(lbuf + P.off_lnorm);
   double* R64 = (double*)(ws + P.ws_r64);
   float* Rl = (float*)(ws + P.ws_rl);
   float* D = (float*)(ws + P.ws_d);
@@ -564,21 +732,30 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   float* xinv = (float*)(ws + P.ws_xsc + 4 * P.m);
   double* part = (double*)(ws + P.ws_part);
   double* dnorm = (double*)(ws + P.ws_norm);
+  unsigned* colmax = (unsigned*)(ws + P.ws_colmax);
+  double* dpart = (double*)(ws + P.ws_dpart);
+  double* dres = dpart + crt::kStatSlabs * crt::kRecBlocks;
+  const double* rres = (const double*)(ws + P.ws_rpart) + 4 * crt::kRecBlocks;
 
+  // ||L||_F^2, the residue bit count a (both stored by trsm_invert_diag), max |B|
   double h[4];
-  // ||L||_F (stored by trsm_invert_diag) and max |B| for the first scale.
+  int a = 0;
+  double lnorm2 = 0.0;
   TRSM_HIP(launch_sumsq_max(B, ldb, n, k, part, dnorm, s));
   TRSM_HIP(hipMemcpyAsync(h, dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  double lnorm = 0.0;
-  TRSM_HIP(hipMemcpyAsync(&lnorm, d_lnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  TRSM_HIP(hipMemcpyAsync(&lnorm2, lbuf + P.off_lnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  TRSM_HIP(hipMemcpyAsync(&a, lbuf + P.off_crt_a, sizeof(int), hipMemcpyDeviceToHost, s));
   TRSM_HIP(hipStreamSynchronize(s));
-  lnorm = sqrt(lnorm);
+  const double lnorm = sqrt(lnorm2);
   const bool alias = (const void*)X == (const void*)B;
-  const double u = ldexp(1.0, -53);
 
   double scale = pow2_scale_for(h[1]);
-  TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, amax, xinv, s));
-  TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, true, s));
+  // the first sweep's result is rounded to about 8 bits before the first
+  // residual, so its diagonal apply may run in 16 bits as well
+  const bool coarse = !(P.flags & TRSM_FLAG_NO_REFINE) && !std::is_same<TL, fp8_t>::value;
+  TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, amax, xinv, s,
+                         coarse ? (const TL*)(lbuf + P.off_linv16) : nullptr,
+                         (const float*)(lbuf + P.off_linv16_rs)));
   if (info) {
     info->iterations = 0;
     info->converged = 0;
@@ -587,52 +764,89 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
     info->unrefined_error = -1.0;
   }
   if (P.flags & TRSM_FLAG_NO_REFINE) {
+    TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, true, s));
     if (info) info->converged = 1;
     return TRSM_OK;
   }
   if (alias) return TRSM_EINVAL;  // refinement needs the original B (checked earlier too)
 
-  double prev_corr = -1.0;
-  for (int it = 1; it <= 10; ++it) {
-    // R = B - L X (binary64) and its norms, ||X||
-    TRSM_HIP(gemm_simple<double>(L, ldl, X, ldx, B, ldb, R64, k, n, k, n, -1.0, 1.0, G_A_LOWER, s));
-    TRSM_HIP(launch_sumsq_max(R64, k, n, k, part, dnorm, s));
-    TRSM_HIP(launch_sumsq_max(X, ldx, n, k, part, dnorm + 2, s));
-    TRSM_HIP(hipMemcpyAsync(h, dnorm, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  int b0 = 0, b1 = 0;
+  const int P0 = crt_moduli(a, 7, n, &b0);
+  const int P1 = crt_moduli(a, 20, n, &b1);
+  if (P0 < 0 || P1 < 0) return TRSM_EINVAL;
+
+  // correction pieces: the first three stay in their own binary32 buffers
+  // and X is assembled from them at the end (one binary64 pass); from the
+  // fourth on they are added to X as they come
+  float* piece[3] = {D, (float*)(ws + P.ws_d1), (float*)(ws + P.ws_d2)};
+  int pshift[3] = {0, 0, 0};
+  double prev = -1.0, xnorm = 0.0;
+  float* cur = D;
+  for (int j = 0; j <= 10; ++j) {
+    // ||D|| and the column maxima of the new correction
+    TRSM_HIP(launch_fill_u32(colmax, k, 0u, s));
+    TRSM_HIP(crt::launch_dstats<float>(cur, k, n, k, colmax, dpart, dres, s));
+    const int yshift = -ilogb(scale);   // the correction is cur 2^yshift
+    if (j > 0) {
+      double dn2 = 0.0;
+      TRSM_HIP(hipMemcpyAsync(&dn2, dres, sizeof(double), hipMemcpyDeviceToHost, s));
+      TRSM_HIP(hipStreamSynchronize(s));
+      const double corr = (xnorm > 0) ? ldexp(sqrt(dn2), yshift) / xnorm : ldexp(sqrt(dn2), yshift);
+      if (info) {
+        info->iterations = j;
+        info->correction = corr;
+        if (j == 1) info->unrefined_error = corr;
+      }
+      bool done = corr <= 1e-15;
+      if (!done && prev > 0) {
+        const double rho = corr / prev;
+        done = rho <= 0.5 && corr * rho <= 1e-14;
+      }
+      prev = corr;
+      if (done || j == 10) {
+        if (j <= 2)
+          TRSM_HIP(crt::launch_assemble(piece[0], pshift[0], j >= 2 ? piece[1] : cur, j >= 2 ? pshift[1] : yshift,
+                                        j >= 2 ? cur : nullptr, yshift, k, X, ldx, n, k, false, s));
+        else
+          TRSM_HIP(crt::launch_assemble(cur, yshift, nullptr, 0, nullptr, 0, k, X, ldx, n, k, true, s));
+        if (done && info) info->converged = 1;
+        return done ? TRSM_OK : TRSM_ENOTCONVERGED;
+      }
+    }
+    // R -= L round(cur), exactly; the rounded piece stays in cur
+    const bool first = j == 0;
+    if (j == 2)   // X from the first two pieces; later pieces are added as they come
+      TRSM_HIP(crt::launch_assemble(piece[0], pshift[0], piece[1], pshift[1], nullptr, 0, k, X, ldx,
+                                    n, k, false, s));
+    TRSM_TRY(crt_residual(P, L, ldl, lbuf, cur, yshift, first ? b0 : b1, first ? P0 : P1,
+                          first ? B : R64, first ? ldb : k, X, ldx, j >= 2 ? 2 : 0, ws, s));
+    if (j < 3) pshift[j] = yshift;
+    TRSM_HIP(hipMemcpyAsync(h, rres, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     TRSM_HIP(hipStreamSynchronize(s));
-    const double rn = sqrt(h[0]), xn = sqrt(h[2]);
-    const double berr = (lnorm * xn > 0) ? rn / (lnorm * xn) : rn;
-    if (info) info->backward_error = berr;
-    if (berr <= 4.0 * u || rn == 0.0) {
+    const double rn = sqrt(h[0]);
+    if (j >= 2) {
+      xnorm = sqrt(h[2]);
+    } else {
+      // ||X|| of the pieces so far: ||piece_0|| for the first (its rounding
+      // changes the norm by less than 2^-7), good enough for relative tests
+      double dn2 = 0.0;
+      TRSM_HIP(hipMemcpyAsync(&dn2, dres, sizeof(double), hipMemcpyDeviceToHost, s));
+      TRSM_HIP(hipStreamSynchronize(s));
+      if (first) xnorm = ldexp(sqrt(dn2), yshift);
+    }
+    if (info) info->backward_error = (lnorm * xnorm > 0) ? rn / (lnorm * xnorm) : rn;
+    if (rn == 0.0) {
+      // exact: X is complete (from the third piece on it was updated in place)
+      if (j < 2)
+        TRSM_HIP(crt::launch_assemble(piece[0], pshift[0], j == 1 ? piece[1] : nullptr, pshift[1],
+                                      nullptr, 0, k, X, ldx, n, k, false, s));
       if (info) info->converged = 1;
       return TRSM_OK;
     }
-    scale = pow2_scale_for(h[1]);
-    TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, R64, k, scale, Rl, D, XlowT, amax, xinv, s));
-    TRSM_HIP(launch_axpy_f32_to_f64(D, k, X, ldx, n, k, 1.0 / scale, false, s));
-    // ||D|| (binary32 values, exact in binary64) for the stopping test
-    TRSM_HIP(launch_copy2d<float, double>(D, k, R64, k, n, k, 1.0 / scale, s));
-    TRSM_HIP(launch_sumsq_max(R64, k, n, k, part, dnorm, s));
-    TRSM_HIP(hipMemcpyAsync(h, dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    TRSM_HIP(hipStreamSynchronize(s));
-    const double corr = (xn > 0) ? sqrt(h[0]) / xn : sqrt(h[0]);
-    if (info) {
-      info->iterations = it;
-      info->correction = corr;
-      if (it == 1) info->unrefined_error = corr;
-    }
-    // Stop when the correction is negligible, or when the observed
-    // contraction predicts that the next one would be.
-    bool done = corr <= 1e-13;
-    if (!done && prev_corr > 0) {
-      const double rho = corr / prev_corr;
-      done = rho <= 0.1 && corr * rho <= 1e-14;
-    }
-    prev_corr = corr;
-    if (done) {
-      if (info) info->converged = 1;
-      return TRSM_OK;
-    }
+    // the recombination left R in binary32 in Rl (unscaled)
+    scale = 1.0;
+    cur = piece[std::min(j + 1, 2)];
+    TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, nullptr, k, scale, Rl, cur, XlowT, amax, xinv, s));
   }
   return TRSM_ENOTCONVERGED;
 }
@@ -667,6 +881,8 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   if (prec != TRSM_F64 && prec != TRSM_F32 && !is_mixed(prec)) return TRSM_EINVAL;
   if (n0 < 0 || (n0 > 0 && !is_pow2(n0))) return TRSM_EINVAL;
   if ((flags & TRSM_FLAG_RECURSIVE) && is_mixed(prec)) return TRSM_EINVAL;
+  // the residual's int8 products accumulate up to n terms of |x| <= 2^14 in int32
+  if (is_mixed(prec) && n > crt::kMaxN) return TRSM_EINVAL;
   if (flags & ~(TRSM_FLAG_NO_REFINE | TRSM_FLAG_RECURSIVE | TRSM_FLAG_LOOKAHEAD |
                 TRSM_FLAG_LARGE_TILES | TRSM_FLAG_TRANSPOSE | TRSM_FLAG_UPPER))
     return TRSM_EINVAL;
@@ -718,6 +934,24 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     off = align_up(off + 8);
     P->off_lpart = off;
     off = align_up(off + 2 * kNormBlocks * 8 + 16);
+    P->npad = (n + 63) / 64 * 64;
+    P->ldz = (k + 15) / 16 * 16;
+    P->off_crt_e = off;
+    off = align_up(off + (size_t)crt::kPlanes * P->npad * P->npad);
+    P->off_crt_rowmax = off;
+    off = align_up(off + (size_t)n * 8);
+    P->off_crt_rowpart = off;
+    off = align_up(off + (size_t)n * 8);
+    P->off_crt_stats = off;
+    off = align_up(off + 64);
+    P->off_crt_a = off;
+    off = align_up(off + 64);
+    P->off_crt_sl = off;
+    off = align_up(off + (size_t)P->npad * 4);
+    P->off_linv16 = off;
+    off = align_up(off + (size_t)m * n0 * n0 * 2);
+    P->off_linv16_rs = off;
+    off = align_up(off + (size_t)m * n0 * 4);
   }
   if (flags & TRSM_FLAG_TRANSPOSE) {
     const size_t es = elem_size(prec);
@@ -749,12 +983,28 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     off = align_up(off + (size_t)n * k * 4);
     P->ws_xlow = off;
     off = align_up(off + (size_t)n * k * 2);
-    P->ws_xsc = off;                          // per-block max bits and inverse scales
-    off = align_up(off + (size_t)m * 8);
+    P->ws_xsc = off;   // per-block max bits and inverse scales, for X and for the coarse sweep's B'
+    off = align_up(off + (size_t)m * 16);
     P->ws_part = off;
     off = align_up(off + 2 * kNormBlocks * 8);
     P->ws_norm = off;
     off = align_up(off + 8 * 8);
+    P->ws_d1 = off;
+    off = align_up(off + (size_t)n * k * 4);
+    P->ws_d2 = off;
+    off = align_up(off + (size_t)n * k * 4);
+    P->ws_q = off;
+    off = align_up(off + (size_t)crt::kPlanes * k * P->npad);
+    P->ws_z = off;
+    off = align_up(off + (size_t)crt::kPlanes * P->npad * P->ldz);
+    P->ws_colmax = off;
+    off = align_up(off + (size_t)k * 4);
+    P->ws_ty = off;
+    off = align_up(off + (size_t)k * 4);
+    P->ws_rpart = off;
+    off = align_up(off + (size_t)(4 * crt::kRecBlocks + 8) * 8);
+    P->ws_dpart = off;
+    off = align_up(off + (size_t)(crt::kStatSlabs * crt::kRecBlocks + 8) * 8);
   }
   P->ws_split = off;
   P->ws_split_bytes = split_bytes(n * k);
@@ -866,6 +1116,12 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
   if (is_mixed(P->prec)) {
     float* rs = (float*)(base + P->off_rscale);
     if (P->prec == TRSM_MIXED_BF16)
+      TRSM_HIP(launch_rowscale_copy<bf16_t>(L64, m * n0, n0, (bf16_t*)(base + P->off_linv16),
+                                            (float*)(base + P->off_linv16_rs), 1.0f, s));
+    else if (P->prec == TRSM_MIXED_F16)
+      TRSM_HIP(launch_rowscale_copy<f16_t>(L64, m * n0, n0, (f16_t*)(base + P->off_linv16),
+                                           (float*)(base + P->off_linv16_rs), 16384.0f, s));
+    if (P->prec == TRSM_MIXED_BF16)
       TRSM_HIP(launch_lowcopy<bf16_t>((const double*)L, ldl, n, n0, m, (bf16_t*)(base + P->off_llow),
                                       rs, 1.0f, s));
     else if (P->prec == TRSM_MIXED_FP8)
@@ -879,6 +1135,19 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
     double* res = part + 2 * kNormBlocks;
     TRSM_HIP(launch_sumsq_lower<double>((const double*)L, ldl, n, part, res, s));
     TRSM_HIP((launch_copy2d<double, double>(res, 1, (double*)(base + P->off_lnorm), 1, 1, 1, 1.0, s)));
+    // residue planes of L's strictly lower part for the residual's exact
+    // integer products; the bit count a follows from L's magnitudes
+    double* rowmax = (double*)(base + P->off_crt_rowmax);
+    double* stats = (double*)(base + P->off_crt_stats);
+    int* a_dev = (int*)(base + P->off_crt_a);
+    TRSM_HIP(crt::launch_row_stats((const double*)L, ldl, n, rowmax,
+                                   (double*)(base + P->off_crt_rowpart), stats, s));
+    TRSM_HIP(crt::launch_choose_bits(stats, (const double*)(base + P->off_lnorm),
+                                     crt::kTargetBits, a_dev, s));
+    const crt::Table t = crt::make_table(crt::kPlanes);
+    TRSM_HIP(crt::launch_l_residues((const double*)L, ldl, n, P->npad, rowmax, a_dev, t,
+                                    (int8_t*)(base + P->off_crt_e), P->npad,
+                                    P->npad * P->npad, (int*)(base + P->off_crt_sl), s));
   }
   return TRSM_OK;
 }
