@@ -121,9 +121,8 @@ int trsm_last_hip_error(void);
  *  otherwise n0 must be a power of two >= 1 (n0 >= n means the full inversion
  *  approach, m = 1).  Returns TRSM_EINVAL for bad arguments, TRSM_ENOMEM if
  *  the plan object cannot be allocated.  *out receives a new plan, owned by
- *  the caller until trsm_plan_destroy.  A plan owns host metadata and, from
- *  its first trsm_invert_diag on, one device status word (8 bytes) on the
- *  device that was current then.
+ *  the caller until trsm_plan_destroy.  A plan owns host metadata only (the
+ *  lookahead flag adds a side stream and events, made on first use).
  */
 trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0,
                       uint32_t flags, trsm_plan_t* out);
@@ -180,10 +179,13 @@ trsm_status trsm_plan_destroy(trsm_plan_t plan);
  * block b at Linv + b*n0*n0 binary64 values, row-major, zeros above the
  * diagonal; a ragged last block (n0 not dividing n) is padded with the
  * identity.  Mixed and F32 plans also store lower-precision copies behind
- * the binary64 inverses.  Asynchronous.  A zero or non-finite diagonal entry
- * is recorded on the device; read it with trsm_plan_last_error after the
- * stream has been synchronised.  Returns TRSM_EINVAL for null pointers or
- * ldl < n.
+ * the binary64 inverses.  Asynchronous, and allocates nothing: every device
+ * byte it writes lies in `Linv` (the last 256 bytes of the buffer hold the
+ * status word), and its products run without split-K scratch, so the call
+ * can be captured into a HIP graph.  A zero or non-finite diagonal entry is
+ * recorded in that status word; read it with trsm_plan_last_error after the
+ * stream has been synchronised (the plan remembers the buffer of its last
+ * trsm_invert_diag).  Returns TRSM_EINVAL for null pointers or ldl < n.
  */
 trsm_status trsm_invert_diag(trsm_plan_t plan, const void* L, int64_t ldl, void* Linv,
                              void* stream);
@@ -191,7 +193,9 @@ trsm_status trsm_invert_diag(trsm_plan_t plan, const void* L, int64_t ldl, void*
 /*
  * After synchronising the stream used by trsm_invert_diag: *status is
  * TRSM_ESINGULAR and *index the first row with a zero or non-finite
- * diagonal entry, or TRSM_OK and -1.  Blocking (reads one device word).
+ * diagonal entry, or TRSM_OK and -1 (also before any trsm_invert_diag).
+ * Blocking (reads the status word of the plan's last Linv buffer, which must
+ * still be allocated).
  */
 trsm_status trsm_plan_last_error(trsm_plan_t plan, trsm_status* status, int64_t* index);
 

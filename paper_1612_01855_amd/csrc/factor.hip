@@ -692,9 +692,14 @@ trsm_status sizes_for(int64_t n, int64_t nb, Sizes* z, bool lu = false) {
         pow2_at_least(std::max<int64_t>(n, kLeaf)));
   if (nb < kLeaf || nb > kMaxNb || (nb & (nb - 1))) return TRSM_EINVAL;
   if (n > (int64_t)1 << 20) return TRSM_EINVAL;
+  // no block larger than the matrix rounded up to a power of two (the cap a
+  // TRSM plan puts on n0), so that the inverted blocks keep a plan's layout
+  nb = std::min<int64_t>(nb, pow2_at_least(std::max<int64_t>(n, kLeaf)));
   const int64_t m = n > 0 ? (n + nb - 1) / nb : 0;
   z->nb = nb;
-  z->linv = al((size_t)m * nb * nb * 8);
+  // a TRSM_F64 plan's Linv buffer with n0 = nb: the packed inverses, then
+  // the 256 bytes of that plan's status word
+  z->linv = al((size_t)m * nb * nb * 8) + al(8);
   size_t off = kAl;                                 // status word
   z->off_w = off;
   off += al((size_t)nb * nb * 8);

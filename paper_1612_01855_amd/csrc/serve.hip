@@ -173,8 +173,10 @@ namespace {
 
 size_t factor_bytes(int64_t n, int64_t n0, bool chol) {
   const int64_t m = ceil_div(n, n0);
+  // the binary64 inverses take a TRSM_F64 plan's whole Linv buffer (the
+  // packed blocks and the inversion's status word)
   size_t b = al((size_t)n * round_up(n, 2) * 8) + al((size_t)n * round_up(n, 4) * 4) +
-             al((size_t)m * n0 * n0 * 8) + al((size_t)m * n0 * n0 * 4);
+             al((size_t)m * n0 * n0 * 8) + al(8) + al((size_t)m * n0 * n0 * 4);
   if (chol)
     b += al((size_t)n * round_up(n, 2) * 8) + al((size_t)n * round_up(n, 4) * 4) +
          al((size_t)m * n0 * n0 * 4);
@@ -515,7 +517,7 @@ trsm_status register_factor(trsm_server_t S, const double* L, int64_t n, int64_t
   f.L64 = (double*)p; p += al((size_t)n * f.ld64 * 8);
   f.ld32 = round_up(n, 4);
   f.L32 = (float*)p; p += al((size_t)n * f.ld32 * 4);
-  f.Linv64 = (double*)p; p += al((size_t)f.m * f.n0 * f.n0 * 8);
+  f.Linv64 = (double*)p; p += al((size_t)f.m * f.n0 * f.n0 * 8) + al(8);
   f.Linv32 = (float*)p; p += al((size_t)f.m * f.n0 * f.n0 * 4);
   if (chol) {
     f.U64 = (double*)p; p += al((size_t)n * f.ld64 * 8);
@@ -526,6 +528,11 @@ trsm_status register_factor(trsm_server_t S, const double* L, int64_t n, int64_t
   trsm_plan_t plan = nullptr;
   trsm_status st = trsm_plan(n, 1, TRSM_F64, f.n0, 0, &plan);   // the factor's own block size
   hipError_t e = hipSuccess;
+  if (st == TRSM_OK) {
+    trsm_plan_info pi;
+    st = trsm_plan_get_info(plan, &pi);
+    if (st == TRSM_OK && pi.linv_bytes > al((size_t)f.m * f.n0 * f.n0 * 8) + al(8)) st = TRSM_EINVAL;
+  }
   if (st == TRSM_OK) {
     e = launch_copy2d<double, double>(L, ldl, f.L64, f.ld64, n, n, 1.0, s);
     if (e == hipSuccess) e = launch_copy2d<double, float>(L, ldl, f.L32, f.ld32, n, n, 1.0, s);

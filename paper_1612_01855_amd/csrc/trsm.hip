@@ -214,9 +214,11 @@ struct trsm_plan_s {
   size_t ws_d1 = 0, ws_d2 = 0;   // the second and third correction pieces
   int64_t npad = 0, ldz = 0;
   size_t ws_bytes = 0;
-  unsigned long long* d_bad = nullptr;   // first singular row (device word)
-  void* d_split = nullptr;               // split-K scratch of the inversion
-  size_t inv_split_bytes = 0;
+  // first singular row: a device word inside the caller's Linv buffer (at
+  // off_status), written by the last trsm_invert_diag; last_linv remembers
+  // that buffer for trsm_plan_last_error
+  size_t off_status = 0;
+  const void* last_linv = nullptr;
   LaunchTimer timer;
   // lookahead: a second stream and the events that order the two
   hipStream_t side = nullptr;
@@ -713,9 +715,11 @@ int crt_moduli(int a, int bmin, int64_t n, int* b_out) {
 // lower part is rounded to a bits (relative to each row's largest entry), and
 // binary64 work is limited to one rounding per element.  The first piece is
 // rounded coarsely (about 8 bits: the next correction removes that error as
-// well), later ones to 20+ bits.  Stop when the next correction predicted from
-// the observed contraction, ||D_j|| * (||D_j|| / ||D_{j-1}||), falls below
-// 1e-14 ||X||, or a correction falls below 1e-15 ||X||; at most 10 corrections.
+// well), later ones to 20+ bits.  Stop when the exact residual of the pieces
+// so far gives a backward error ||R|| / (||L|| ||X||) <= 4u, when the next
+// correction predicted from the observed contraction,
+// ||D_j|| * (||D_j|| / ||D_{j-1}||), falls below 1e-14 ||X||, or when a
+// correction falls below 1e-15 ||X||; at most 10 corrections.
 template <typename TL>
 trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, const char* lbuf,
                         const double* B, int64_t ldb, double* X, int64_t ldx, char* ws,
@@ -748,6 +752,7 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   TRSM_HIP(hipStreamSynchronize(s));
   const double lnorm = sqrt(lnorm2);
   const bool alias = (const void*)X == (const void*)B;
+  const double u = ldexp(1.0, -53);
 
   double scale = pow2_scale_for(h[1]);
   // the first sweep's result is rounded to about 8 bits before the first
@@ -834,9 +839,11 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
       TRSM_HIP(hipStreamSynchronize(s));
       if (first) xnorm = ldexp(sqrt(dn2), yshift);
     }
-    if (info) info->backward_error = (lnorm * xnorm > 0) ? rn / (lnorm * xnorm) : rn;
-    if (rn == 0.0) {
-      // exact: X is complete (from the third piece on it was updated in place)
+    const double berr = (lnorm * xnorm > 0) ? rn / (lnorm * xnorm) : rn;
+    if (info) info->backward_error = berr;
+    if (rn == 0.0 || berr <= 4.0 * u) {
+      // the pieces so far are backward stable (the residual is exact for
+      // them): X is their sum (from the third piece on it was updated in place)
       if (j < 2)
         TRSM_HIP(crt::launch_assemble(piece[0], pshift[0], j == 1 ? piece[1] : nullptr, pshift[1],
                                       nullptr, 0, k, X, ldx, n, k, false, s));
@@ -966,6 +973,8 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
     P->off_uinv = off;
     off = align_up(off + (size_t)m * n0 * n0 * elem_size(prec));
   }
+  P->off_status = off;
+  off = align_up(off + 8);
   P->linv_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : off;
   // workspace
   off = 0;
@@ -1010,8 +1019,6 @@ trsm_status trsm_plan(int64_t n, int64_t k, trsm_precision prec, int64_t n0, uin
   P->ws_split_bytes = split_bytes(n * k);
   off = align_up(off + P->ws_split_bytes);
   P->ws_bytes = off;
-  // inversion levels: batch x h x h outputs, at most n * n0 / 4 elements
-  P->inv_split_bytes = (flags & TRSM_FLAG_RECURSIVE) ? 0 : split_bytes(n * n0 / 4);
   *out = P;
   return TRSM_OK;
 }
@@ -1035,8 +1042,6 @@ trsm_status trsm_plan_get_info(trsm_plan_t P, trsm_plan_info* info) {
 
 trsm_status trsm_plan_destroy(trsm_plan_t P) {
   if (!P) return TRSM_OK;
-  if (P->d_bad) (void)hipFree(P->d_bad);
-  if (P->d_split) (void)hipFree(P->d_split);
   P->timer.release();
   for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
   if (P->side) (void)hipStreamDestroy(P->side);
@@ -1055,31 +1060,21 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
   char* base = (char*)Linv;
   double* L64 = (double*)(base + P->off_linv64);
   const int64_t n = P->n, n0 = P->n0, m = P->m;
-  if (!P->d_bad) {
-    // the status word is made on first use, on the current device
-    if (hipMalloc((void**)&P->d_bad, sizeof(unsigned long long)) != hipSuccess) {
-      P->d_bad = nullptr;
-      return TRSM_ENOMEM;
-    }
-  }
-  if (!P->d_split && P->inv_split_bytes && P->leaf < n0) {
-    if (hipMalloc(&P->d_split, P->inv_split_bytes) != hipSuccess) {
-      P->d_split = nullptr;
-      return TRSM_ENOMEM;
-    }
-  }
+  // the status word lives in the caller's buffer; the inversion's products
+  // run without split-K scratch, so the call allocates nothing
+  unsigned long long* bad = (unsigned long long*)(base + P->off_status);
+  P->last_linv = Linv;
   const bool large = P->flags & TRSM_FLAG_LARGE_TILES;
   TilePolicyScope tile_scope(large);
-  SplitScope split_scope(large ? nullptr : P->d_split,
-                         (P->d_split && !large) ? (int64_t)P->inv_split_bytes : 0);
-  TRSM_HIP(hipMemsetAsync(P->d_bad, 0xFF, sizeof(unsigned long long), s));
+  SplitScope split_scope(nullptr, 0);
+  TRSM_HIP(launch_fill_u32((unsigned*)bad, 2, 0xFFFFFFFFu, s));
   // an upper plan inverts the transposed blocks U_ii^T (lower) and
   // transposes the inverses back below
   const bool upper = P->flags & TRSM_FLAG_UPPER;
   if (P->prec == TRSM_F32)
-    TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, P->d_bad, s, upper));
+    TRSM_HIP(launch_extract_diag<float>((const float*)L, ldl, n, n0, m, L64, bad, s, upper));
   else
-    TRSM_HIP(launch_extract_diag<double>((const double*)L, ldl, n, n0, m, L64, P->d_bad, s, upper));
+    TRSM_HIP(launch_extract_diag<double>((const double*)L, ldl, n, n0, m, L64, bad, s, upper));
   TRSM_HIP(launch_trtri_leaf(L64, n0, m, P->leaf, s));
   if (P->leaf < n0) {
     TRSM_HIP(rec_tri_inv_levels(L64, n0, m, P->leaf, s));
@@ -1155,7 +1150,9 @@ trsm_status trsm_invert_diag(trsm_plan_t P, const void* L, int64_t ldl, void* Li
 trsm_status trsm_plan_last_error(trsm_plan_t P, trsm_status* status, int64_t* index) {
   if (!P || !status || !index) return TRSM_EINVAL;
   unsigned long long v = ~0ull;
-  if (P->d_bad) TRSM_HIP(hipMemcpy(&v, P->d_bad, sizeof(v), hipMemcpyDeviceToHost));
+  if (P->last_linv)
+    TRSM_HIP(hipMemcpy(&v, (const char*)P->last_linv + P->off_status, sizeof(v),
+                       hipMemcpyDeviceToHost));
   if (v == ~0ull) {
     *status = TRSM_OK;
     *index = -1;
@@ -1166,9 +1163,15 @@ trsm_status trsm_plan_last_error(trsm_plan_t P, trsm_status* status, int64_t* in
   return TRSM_OK;
 }
 
-trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv, const void* B,
-                       int64_t ldb, void* X, int64_t ldx, void* workspace, void* stream,
-                       trsm_info* info) {
+}  // extern "C"
+
+namespace {
+
+// trsm_solve's body; the split-K scratch of the products is the given
+// region (the plan's section of the workspace).
+trsm_status solve_impl(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv, const void* B,
+                       int64_t ldb, void* X, int64_t ldx, void* workspace, void* split,
+                       int64_t split_bytes, void* stream, trsm_info* info) {
   if (!P) return TRSM_EINVAL;
   if (info) {
     info->iterations = 0;
@@ -1195,7 +1198,7 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   char* ws = (char*)workspace;
   const bool large = P->flags & TRSM_FLAG_LARGE_TILES;
   TilePolicyScope tile_scope(large);
-  SplitScope split_scope(large ? nullptr : ws + P->ws_split, large ? 0 : (int64_t)P->ws_split_bytes);
+  SplitScope split_scope(large ? nullptr : split, large ? 0 : split_bytes);
   if (rec) {
     if (P->prec == TRSM_F64) {
       if (X != B) TRSM_HIP(launch_copy2d<double, double>((const double*)B, ldb, (double*)X, ldx, n, k, 1.0, s));
@@ -1240,6 +1243,20 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   }
   return TRSM_EINVAL;
 }
+
+}  // namespace
+
+extern "C" {
+
+trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv, const void* B,
+                       int64_t ldb, void* X, int64_t ldx, void* workspace, void* stream,
+                       trsm_info* info) {
+  if (!P) return TRSM_EINVAL;
+  char* ws = (char*)workspace;
+  return solve_impl(P, L, ldl, Linv, B, ldb, X, ldx, workspace, ws ? ws + P->ws_split : nullptr,
+                    ws ? (int64_t)P->ws_split_bytes : 0, stream, info);
+}
+
 
 size_t trsm_residual_workspace_bytes(int64_t n, int64_t k) {
   if (n < 0 || k < 0) return 0;

@@ -98,6 +98,14 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1612_01855_amd.build` (no fallback path exists)")
+    # torch ships its own HIP runtime under the same soname as the one the
+    # library links; loading torch first makes the library bind to that one,
+    # so that one process never holds two HIP runtimes (device memory from
+    # one is unknown to the other)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     i64, u32, vp, i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
     lib.trsm_status_string.argtypes = [i32]
@@ -461,10 +469,11 @@ class Solver:
         if X is None:
             X = torch.empty_like(B)
         dt = self._dtype()
-        trsm_solve(self.plan, _dev(L, dt, "L"), _ld(L), linv_ptr or self.linv_ptr,
-                   _dev(B, dt, "B"), _ld(B),
-                   _dev(X, dt, "X"), _ld(X), self.workspace_ptr,
-                   _stream_handle(torch, B.device), info)
+        # TRSM_OK, or TRSM_ENOTCONVERGED (X then holds the last iterate)
+        self.last_status = trsm_solve(self.plan, _dev(L, dt, "L"), _ld(L),
+                                      linv_ptr or self.linv_ptr, _dev(B, dt, "B"), _ld(B),
+                                      _dev(X, dt, "X"), _ld(X), self.workspace_ptr,
+                                      _stream_handle(torch, B.device), info)
         return X
 
     def last_error(self):
@@ -619,6 +628,14 @@ def lu_solve(A, B, nb: int = 0):
     f.factor(F)
     fwd = Solver.create(n, k, "f64", n0=f.nb, device=B.device)
     up = Solver.create(n, k, "f64", 0, FLAG_UPPER, device=B.device)
+    if fwd.info.n0 != f.nb:
+        # a plan caps n0 at the next power of two >= n (below the 64-row
+        # factorization leaf only for n <= 32): the blocks' row stride would
+        # not match the plan's
+        fwd.close()
+        up.close()
+        raise ValueError(f"lu_solve: the factorization's {f.nb}-row inverted blocks do not fit "
+                         f"a plan for n = {n} (its block size is {fwd.info.n0})")
     try:
         Y = fwd.solve(F, B.contiguous(), linv_ptr=f.linv_ptr)
         up.invert(F)

@@ -290,6 +290,15 @@ def test_lu_sizes_and_validation_without_gpu(T):
     for bad_nb in (32, 96, 8192):
         with pytest.raises(T.TrsmError):
             T.trsm_lu_sizes(100, bad_nb)
+    # a block beyond the next power of two >= n is cut to it (a plan's n0 cap),
+    # and the inverse buffer is a TRSM_F64 plan's Linv buffer for that n0
+    nb, lb, _ = T.trsm_lu_sizes(100, 256)
+    assert nb == 128
+    p = T.trsm_plan(100, 5, T.F64, 128, 0)
+    try:
+        assert T.trsm_plan_get_info(p).linv_bytes == lb
+    finally:
+        T.trsm_plan_destroy(p)
     lib = T._lib
     fake = 1 << 20
     assert lib.trsm_lu_factor(64, None, 64, 0, fake, fake, fake, None) == T.EINVAL

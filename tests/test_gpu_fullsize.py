@@ -44,9 +44,11 @@ def sample_cols(k, seed):
     return np.sort(np.concatenate([[0, k - 1], pick]))
 
 
-def gpu_solve_cols(torch, T, Ld, Bd, precision, n0=0, flags=0, info=None, cols=None):
+def gpu_solve_cols(torch, T, Ld, Bd, precision, n0=0, flags=0, info=None, cols=None,
+                   status=None):
     """Plan, invert, solve on the GPU (as the benchmark does); return the
-    requested columns of X as float64 on the host, and the full X tensor."""
+    requested columns of X as float64 on the host, and the full X tensor
+    (the solve's status is appended to `status` when given)."""
     n, k = Bd.shape
     s = T.Solver.create(n, k, precision, n0, flags, device=Bd.device)
     try:
@@ -54,6 +56,8 @@ def gpu_solve_cols(torch, T, Ld, Bd, precision, n0=0, flags=0, info=None, cols=N
             s.invert(Ld)
         X = s.solve(Ld, Bd, info=info)
         torch.cuda.synchronize()
+        if status is not None:
+            status.append(s.last_status)
     finally:
         s.close()
     idx = torch.from_numpy(cols).to(Bd.device)
@@ -158,6 +162,58 @@ def test_cholesky_n16384_k32768_f64(torch, T):
     assert err <= TOL64
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cholesky_n16384_k2048(torch, T, prec):
+    # the middle of the n/k sweep, in the configuration the suite times (n0
+    # from the plan: the recorded autotuner choice or the cost model)
+    n, k = 16384, 2048
+    Ld = gen.chol_lower_on(torch, "cuda", n, 8)
+    B = gen.rhs(n, k, 8)
+    if prec == "f32":
+        Ld = Ld.float()
+        B = B.astype(np.float32)
+    cols = sample_cols(k, 109)
+    Xs, X = gpu_solve_cols(torch, T, Ld, torch.from_numpy(B).cuda(), prec, cols=cols)
+    L = Ld.double().cpu().numpy()
+    del Ld, X
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle_cols(L, B.astype(np.float64), cols))
+    log(f"cholesky n={n} k={k} {prec}: sampled rel err {err:.2e}")
+    assert err <= (TOL32 if prec == "f32" else TOL64)
+
+
+def test_cholesky_n16384_k32768_f32(torch, T):
+    # the wide end of the n/k sweep in binary32 (the oracle on the rounded inputs)
+    n, k = 16384, 32768
+    Ld = gen.chol_lower_on(torch, "cuda", n, 10).float()
+    B = gen.rhs(n, k, 10).astype(np.float32)
+    cols = sample_cols(k, 110)
+    Xs, X = gpu_solve_cols(torch, T, Ld, torch.from_numpy(B).cuda(), "f32", cols=cols)
+    L = Ld.double().cpu().numpy()
+    del Ld, X
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle_cols(L, B.astype(np.float64), cols))
+    log(f"cholesky n={n} k={k} f32: sampled rel err {err:.2e}")
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("n0", [64, 8192])
+def test_f32_n8192_k8192_blockings(torch, T, n0):
+    # the ends of the n0 sweep in binary32 (n0 = n: the whole triangle inverted)
+    n = k = 8192
+    L, B = gen.easy_system(n, k, 11, upper=np.nan)
+    L32, B32 = L.astype(np.float32), B.astype(np.float32)
+    del L, B
+    cols = sample_cols(k, 111)
+    Xs, X = gpu_solve_cols(torch, T, torch.from_numpy(L32).cuda(), torch.from_numpy(B32).cuda(),
+                           "f32", n0=n0, cols=cols)
+    del X
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle_cols(L32.astype(np.float64), B32.astype(np.float64), cols))
+    log(f"n=k={n} f32 n0={n0}: sampled rel err {err:.2e}")
+    assert err <= TOL32
+
+
 @pytest.mark.parametrize("n0,flags", [(64, 0), (8192, 0), (0, 2)])
 def test_n8192_k8192_blockings(torch, T, n0, flags):
     # smallest and largest n0 of the sweep (n0 = n is the full inversion), and
@@ -174,7 +230,7 @@ def test_n8192_k8192_blockings(torch, T, n0, flags):
     assert err <= TOL64
 
 
-@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
 def test_mixed_hard_n16384_k16384(torch, T, prec):
     # cond(L) ~ 1e6: the refined solve must reach binary64 backward stability;
     # forward agreement with the oracle is bounded by cond(L) u, not 1e-12
@@ -183,8 +239,9 @@ def test_mixed_hard_n16384_k16384(torch, T, prec):
     B = gen.rhs(n, k, 6)
     cols = sample_cols(k, 106)
     info = T.Info()
+    status = []
     Xs, X = gpu_solve_cols(torch, T, Ld, torch.from_numpy(B).cuda(), prec, info=info,
-                           cols=cols)
+                           cols=cols, status=status)
     assert bool(torch.isfinite(X).all())
     L = Ld.cpu().numpy()
     del Ld, X
@@ -194,11 +251,13 @@ def test_mixed_hard_n16384_k16384(torch, T, prec):
     berr_or = oracle.backward_err(L, oracle.trsm(L, Bs), Bs)
     log(f"hard {prec} full size: {info.iterations} corrections, converged={info.converged}, "
         f"sampled backward error {berr:.2e} (oracle's own {berr_or:.2e})")
-    if info.converged:
+    if prec in ("bf16", "f16"):
+        assert info.converged == 1 and status[0] == T.OK
         assert berr <= 1e-14
     else:
-        # not converged is reported, never hidden behind a passing stop test
-        assert info.backward_error > 4 * 2.0 ** -53
+        # the fp8 experiment either converges or returns TRSM_ENOTCONVERGED
+        assert (info.converged == 1 and status[0] == T.OK and berr <= 1e-14) or \
+            (info.converged == 0 and status[0] == T.ENOTCONVERGED)
 
 
 def test_transposed_f64_n16384_k16384(torch, T):

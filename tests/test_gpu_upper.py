@@ -160,3 +160,25 @@ def test_lu_solve_helper(torch, T):
     A[300, 300] = np.nan
     with pytest.raises(T.TrsmError):
         T.lu_solve(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), nb=128)
+
+
+@pytest.mark.parametrize("n,nb", [(100, 256), (65, 0), (1000, 1024)])
+def test_lu_solve_block_size_beyond_the_matrix(torch, T, n, nb):
+    # a requested block larger than the next power of two >= n is cut to it,
+    # the cap a plan puts on n0, so the inverted blocks keep the plan's layout
+    A = gen.diag_dominant(n, 31)
+    B = gen.rhs(n, 3, 31)
+    X = T.lu_solve(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), nb=nb)
+    err = oracle.rel_fro_err(X.cpu().numpy(), np.linalg.solve(A, B))
+    log(f"  lu_solve n={n} nb={nb}: rel err {err:.2e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 20])
+def test_lu_solve_refuses_blocks_a_plan_cannot_read(torch, T, n):
+    # below n = 33 a plan's n0 is under the factorization's 64-row leaf: the
+    # helper refuses instead of reading the blocks with the wrong row stride
+    A = gen.diag_dominant(n, 32)
+    B = gen.rhs(n, 2, 32)
+    with pytest.raises(ValueError):
+        T.lu_solve(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
