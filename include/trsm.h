@@ -229,6 +229,29 @@ trsm_status trsm_solve(trsm_plan_t plan, const void* L, int64_t ldl, const void*
                        void* stream, trsm_info* info);
 
 /*
+ * trsm_solve_noalloc -- trsm_solve for binary64 and binary32 plans without
+ * a workspace argument and without any allocation: for callers that cannot
+ * allocate device memory (code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid allocation).
+ *  The workspace is a static device array of trsm_solve_noalloc_max_bytes()
+ *  bytes (2 MiB), one copy per GPU, held until the process ends; its
+ *  address on the current device is looked up on the first call there (the
+ *  stream must belong to the current device).  The running right-hand side
+ *  (n * k elements of the plan's precision, rounded up to 256 bytes) must
+ *  fit in it: larger plans return TRSM_ENOMEM before any device work; the
+ *  rest of the array holds split-K partial products.  Mixed-precision plans,
+ *  lookahead plans and plans with per-launch timing on return TRSM_EINVAL.
+ *  Every call on a GPU shares that GPU's array, which keeps the last call's
+ *  contents, so calls that overlap on one GPU (other streams or threads)
+ *  race; serialize them.  Other arguments and results are trsm_solve's; X
+ *  agrees with trsm_solve's up to the rounding of split-K sums.
+ */
+size_t trsm_solve_noalloc_max_bytes(void);
+trsm_status trsm_solve_noalloc(trsm_plan_t plan, const void* L, int64_t ldl, const void* Linv,
+                               const void* B, int64_t ldb, void* X, int64_t ldx, void* stream,
+                               trsm_info* info);
+
+/*
  * trsm_residual -- R = B - L X in binary64 on the matrix cores, followed by
  * deterministic reductions: norms[0] = ||R||_F, norms[1] = ||X||_F,
  * norms[2] = max |R|.  The defect of the postcondition B = L X of Alg.

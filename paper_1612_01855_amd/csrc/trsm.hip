@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1168,7 +1169,8 @@ trsm_status trsm_plan_last_error(trsm_plan_t P, trsm_status* status, int64_t* in
 namespace {
 
 // trsm_solve's body; the split-K scratch of the products is the given
-// region (the plan's section of the workspace).
+// region (the plan's section of the workspace, or part of the static scratch
+// of trsm_solve_noalloc).
 trsm_status solve_impl(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv, const void* B,
                        int64_t ldb, void* X, int64_t ldx, void* workspace, void* split,
                        int64_t split_bytes, void* stream, trsm_info* info) {
@@ -1244,6 +1246,31 @@ trsm_status solve_impl(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
   return TRSM_EINVAL;
 }
 
+// Device scratch of trsm_solve_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses the array's name as an address: its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)2 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+trsm_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  TRSM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TRSM_EINVAL;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    TRSM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return TRSM_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TRSM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1257,6 +1284,28 @@ trsm_status trsm_solve(trsm_plan_t P, const void* L, int64_t ldl, const void* Li
                     ws ? (int64_t)P->ws_split_bytes : 0, stream, info);
 }
 
+size_t trsm_solve_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+trsm_status trsm_solve_noalloc(trsm_plan_t P, const void* L, int64_t ldl, const void* Linv,
+                               const void* B, int64_t ldb, void* X, int64_t ldx, void* stream,
+                               trsm_info* info) {
+  if (!P) return TRSM_EINVAL;
+  // binary64 / binary32 plans on one stream (the lookahead's side stream and
+  // the per-launch timing events would be created on first use)
+  if (is_mixed(P->prec) || (P->flags & TRSM_FLAG_LOOKAHEAD) || P->timer.enabled)
+    return TRSM_EINVAL;
+  // the workspace's running right-hand side must fit the scratch; what is
+  // left of it holds split-K partial products
+  const size_t need = P->ws_split;
+  if (need > kNoAllocScratchBytes) return TRSM_ENOMEM;
+  if (P->n == 0 || P->k == 0) return solve_impl(P, L, ldl, Linv, B, ldb, X, ldx, nullptr, nullptr,
+                                                0, stream, info);
+  void* base = nullptr;
+  TRSM_TRY(scratch_for_current_device(&base));
+  const int64_t split = (int64_t)std::min(P->ws_split_bytes, kNoAllocScratchBytes - need);
+  return solve_impl(P, L, ldl, Linv, B, ldb, X, ldx, base, (char*)base + need, split, stream,
+                    info);
+}
 
 size_t trsm_residual_workspace_bytes(int64_t n, int64_t k) {
   if (n < 0 || k < 0) return 0;

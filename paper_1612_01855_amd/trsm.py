@@ -77,6 +77,7 @@ REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_UNKNOWN = range(5)
 
 EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
+           "trsm_solve_noalloc", "trsm_solve_noalloc_max_bytes",
            "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
            "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
            "trsm_batch_create", "trsm_batch_workspace_bytes",
@@ -124,6 +125,10 @@ def _load():
     lib.trsm_plan_last_error.restype = i32
     lib.trsm_solve.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(Info)]
     lib.trsm_solve.restype = i32
+    lib.trsm_solve_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, ctypes.POINTER(Info)]
+    lib.trsm_solve_noalloc.restype = i32
+    lib.trsm_solve_noalloc_max_bytes.argtypes = []
+    lib.trsm_solve_noalloc_max_bytes.restype = ctypes.c_size_t
     lib.trsm_residual_workspace_bytes.argtypes = [i64, i64]
     lib.trsm_residual_workspace_bytes.restype = ctypes.c_size_t
     lib.trsm_residual.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
@@ -235,6 +240,17 @@ def trsm_solve(plan: int, L: int, ldl: int, Linv: int, B: int, ldb: int, X: int,
     if st not in (OK, ENOTCONVERGED):
         raise TrsmError(st, "trsm_solve")
     return st
+
+
+def trsm_solve_noalloc(plan: int, L: int, ldl: int, Linv: int, B: int, ldb: int, X: int,
+                       ldx: int, stream: int = 0, info: Optional[Info] = None) -> int:
+    """The allocation-free solve; returns the raw status (no exception)."""
+    return int(_lib.trsm_solve_noalloc(plan, L, ldl, Linv, B, ldb, X, ldx, stream,
+                                       ctypes.byref(info) if info is not None else None))
+
+
+def trsm_solve_noalloc_max_bytes() -> int:
+    return int(_lib.trsm_solve_noalloc_max_bytes())
 
 
 def trsm_residual_workspace_bytes(n: int, k: int) -> int:
