@@ -78,11 +78,11 @@ def cpu_baseline(L, B, seconds_hint: float = 15.0):
 
 def serving_bench(args, torch, T, gen, dev, chol=False):
     """Continuous-batching serving: resident factors with cached inverted
-    blocks, Poisson arrivals of binary64 solves (binary32 sweeps + one binary64
-    refinement step).  Reports saturation throughput and p50/p99 latency at a
-    fixed arrival rate.  chol: the factors are registered as Cholesky factors
-    and every request solves A X = B with A = L L^T."""
-    import math
+    blocks, Poisson arrivals of binary64 solves (binary32 sweeps, binary64
+    residuals, refined until each request's own stopping test holds).
+    Reports saturation throughput and p50/p99 latency at fixed arrival rates.
+    chol: the factors are registered as Cholesky factors and every request
+    solves A X = B with A = L L^T."""
     import numpy as np
     nf = args.serve_factors
     sizes = gen.serving_factor_sizes(nf, args.seed + 11)
@@ -124,7 +124,7 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
 
         def drive(bufs, timed_arrivals):
             outstanding = {}
-            lat = []
+            iters = []
             i = 0
             t_start = time.perf_counter()
             flops = 0.0
@@ -137,10 +137,12 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
                     outstanding[t] = (n, r.k)
                     i += 1
                 for t in list(outstanding):
-                    st, status, l_us = T.trsm_serve_poll(srv, t)
+                    st, status, info = T.trsm_serve_poll(srv, t)
                     if st == T.REQ_DONE:
                         n, k = outstanding.pop(t)
-                        lat.append(l_us)
+                        if status != T.OK:
+                            raise RuntimeError(f"serving request: {T.status_string(status)}")
+                        iters.append(info.iterations)
                         flops += (2.0 if chol else 1.0) * float(n) * n * k
                     elif st == T.REQ_ERROR:
                         raise RuntimeError(f"serving request failed: {T.status_string(status)}")
@@ -150,16 +152,18 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
                         time.sleep(min(wait, 2e-4))
                 elif outstanding:
                     time.sleep(5e-5)
-            return time.perf_counter() - t_start, lat, flops
+            return time.perf_counter() - t_start, iters, flops
 
         # saturation: everything submitted at once
         sat = gen.request_stream(min(1000, args.serve_requests), 1.0, nf, args.seed + 21)
         bufs = make_requests(sat)
         drive(bufs[:50], False)                       # warm the kernels
         T.trsm_server_reset_stats(srv)
-        wall, lat, flops = drive(bufs, False)
+        wall, iters, flops = drive(bufs, False)
         sat_rps = len(bufs) / wall
-        log(f"serving: saturation {sat_rps:.0f} requests/s, {flops / wall / 1e12:.2f} TFLOP/s")
+        st = T.trsm_server_stats(srv)
+        log(f"serving: saturation {sat_rps:.0f} requests/s, {flops / wall / 1e12:.2f} TFLOP/s, "
+            f"{st.batches} batches, {st.passes} passes, mean corrections {np.mean(iters):.2f}")
         del bufs
         # Poisson streams at fixed fractions of the saturation rate
         sweep = []
@@ -169,18 +173,17 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
             stream = gen.request_stream(args.serve_requests, rate, nf, args.seed + 31)
             bufs = make_requests(stream)
             T.trsm_server_reset_stats(srv)
-            wall, lat, flops = drive(bufs, True)
-            st = T.trsm_server_stats(srv)
-            lat = np.sort(np.array(lat))
-            p50 = float(lat[max(0, math.ceil(0.5 * len(lat)) - 1)])
-            p99 = float(lat[max(0, math.ceil(0.99 * len(lat)) - 1)])
-            log(f"serving: {len(lat)} requests at {rate:.0f}/s (load {load}): p50 {p50:.0f} us, "
-                f"p99 {p99:.0f} us, {flops / wall / 1e12:.2f} TFLOP/s, {st.batches} batches, "
+            wall, iters, flops = drive(bufs, True)
+            st = T.trsm_server_stats(srv)   # latency: submit -> completion, server side
+            log(f"serving: {st.completed} requests at {rate:.0f}/s (load {load}): "
+                f"p50 {st.p50_us:.0f} us, p99 {st.p99_us:.0f} us, "
+                f"{flops / wall / 1e12:.2f} TFLOP/s, {st.batches} batches, {st.passes} passes, "
                 f"max in flight {st.max_in_flight}")
-            rec = {"load_fraction": load, "rate_hz": round(rate, 1), "requests": len(lat),
-                   "p50_us": round(p50, 1), "p99_us": round(p99, 1),
-                   "mean_us": round(float(lat.mean()), 1),
+            rec = {"load_fraction": load, "rate_hz": round(rate, 1), "requests": int(st.completed),
+                   "p50_us": round(st.p50_us, 1), "p99_us": round(st.p99_us, 1),
+                   "mean_us": round(st.mean_us, 1),
                    "tflops_n2k": round(flops / wall / 1e12, 4), "batches": int(st.batches),
+                   "passes": int(st.passes), "mean_corrections": round(float(np.mean(iters)), 3),
                    "max_in_flight": int(st.max_in_flight)}
             sweep.append(rec)
             if load == args.serve_load:
@@ -189,7 +192,8 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
         out = {"factors": nf, "n_range": [int(sizes.min()), int(sizes.max())],
                "k_range": [1, 512], "saturation_rps": round(sat_rps, 1),
                "hbm_budget_gib": round(budget / 2**30, 2), "n0_max": n0,
-               "precision": "binary64 in/out; binary32 sweeps + one binary64 refinement step",
+               "precision": "binary64 in/out; binary32 sweeps, binary64 residuals, refined per "
+                            "request to ||B-LX||_F <= sqrt(n) 2^-53 ||L||_F ||X||_F",
                "problem": "A X = B, A = L L^T (flops 2 n^2 k)" if chol else "L X = B"}
         out.update(headline)
         out["rate_sweep"] = sweep

@@ -327,43 +327,83 @@ trsm_status trsm_batch_destroy(trsm_batch_t batch);
 /*
  * Serving -- continuous batching of solves against resident factors.
  *
- * trsm_server_create(hbm_budget, max_slots, n0, &srv): the server allocates
- *  ONE device block of hbm_budget bytes on the current device and never more;
+ * Each request is solved by iterative refinement around the sweep of Alg.
+ * It-Inv-TRSM with the factor's cached inverted blocks (Alg.
+ * Diagonal-Inverter, run once at registration):
+ *     X_0 = sweep(B);  R_j = B - L X_j (binary64);  X_{j+1} = X_j + sweep(R_j)
+ * and the work is done in "passes": a request's first pass computes X_0 and,
+ * for a TRSM_F32 factor, its first correction X_1; every later pass applies
+ * one more correction.  After each pass the server evaluates the request's
+ * own stopping test from its binary64 residual and correction norms:
+ *     berr = ||B - L X||_F / (||L||_F ||X||_F)    (||L||_F^2 for A = L L^T)
+ *     corr = ||X_{j+1} - X_j||_F / ||X_{j+1}||_F
+ * The request is converged when R = 0, when berr <= tol (tol = sqrt(n) 2^-53
+ * by default: the normwise stopping test of the mixed-precision refinement of
+ * Buttari, Dongarra, Langou et al., with Frobenius norms), when corr <=
+ * 1e-15, or when the observed contraction rho = corr_j / corr_{j-1} is at
+ * most 1/2 with corr_j rho <= 1e-14.  Otherwise it joins the next batch for
+ * another pass, up to the correction cap, where it ends with
+ * TRSM_ENOTCONVERGED (X then holds the last iterate).  A request whose norms
+ * are not finite also ends with TRSM_ENOTCONVERGED.  Every pass writes the
+ * current iterate to the caller's X.  The tiles and sums of a request are
+ * computed identically whatever else shares its batches, so its result, its
+ * pass count and its info do not depend on the mix.
+ *
+ * trsm_server_create(hbm_budget, max_slots, &srv): the server allocates ONE
+ *  device block of hbm_budget bytes on the current device and never more;
  *  factors and in-flight requests are carved from it ("admission by HBM
- *  budget").  At most max_slots requests are in flight.  n0 (power of two)
- *  is the diagonal block size used for every factor, capped at the next
- *  power of two >= the factor's n (so n0 >= n inverts the whole factor:
- *  each request is then one product per sweep).  A worker thread and four
- *  streams (default priority) are created.  Thread-safe afterwards.
- * trsm_server_register_L(srv, L, n, ldl, &l_id): copies the binary64 lower
- *  triangle of L (device pointer) into the server, makes a binary32 copy and
- *  inverts its diagonal blocks (Alg. Diagonal-Inverter) once; blocking.
- *  TRSM_ENOMEM if it does not fit the budget, TRSM_ESINGULAR for a zero or
- *  non-finite diagonal.
- * trsm_server_register_chol(srv, L, n, ldl, &l_id): the same for a Cholesky
- *  factor: requests on it solve A X = B for A = L L^T (forward sweep with L,
- *  backward sweep with L^T, binary64 residual B - L (L^T X), one refinement
- *  step).  The server also keeps L^T and its inverted blocks (about twice the
- *  memory of a triangular factor); n^2 k flops count twice for these.  Their
- *  block size is min(n0, 512): larger inverted blocks leave the single
- *  refinement step too little accuracy margin on A's squared conditioning.
+ *  budget").  At most max_slots requests are in flight.  A worker thread and
+ *  four streams (default priority) are created, plus pinned host memory for
+ *  the per-request norms (32 bytes a slot).  Thread-safe afterwards.
+ *  Defaults: block size n0 = min(next power of two >= n, 4096) per factor
+ *  (so factors of up to 4096 rows are inverted whole: each sweep is one
+ *  product), tolerance sqrt(n) 2^-53, at most 10 corrections.
+ * trsm_server_create_ex(hbm_budget, max_slots, &options, &srv): the same with
+ *  options (a zero field keeps its default): n0 (a power of two; capped per
+ *  factor at the next power of two >= n; n0 = 64 sweeps with one persistent
+ *  launch per sweep), tolerance (a fixed backward-error bound instead of
+ *  sqrt(n) 2^-53), max_corrections (1 .. 50).
+ * trsm_server_register_L(srv, L, n, ldl, prec, &l_id): copies the binary64
+ *  lower triangle of L (device pointer, row-major; the strict upper part is
+ *  not read) into the server and inverts its diagonal blocks once in binary64;
+ *  blocking.  prec = TRSM_F32: sweeps in binary32 (the server keeps L in
+ *  binary64 for the residual and in binary32, and the inverted blocks in
+ *  binary32); prec = TRSM_F64: sweeps in binary64 (L and the blocks in
+ *  binary64; usually one pass).  Other precisions: TRSM_EINVAL, and so is a
+ *  factor whose ||L||_F^2 is not a normal binary64 number (entries beyond
+ *  about 2^+-500).  TRSM_ENOMEM if it does not fit the budget,
+ *  TRSM_ESINGULAR for a zero or non-finite diagonal.
+ * trsm_server_register_chol(srv, L, n, ldl, prec, &l_id): the same for a
+ *  Cholesky factor: requests on it solve A X = B for A = L L^T (each sweep is
+ *  a forward sweep with L and a backward sweep with L^T; the residual is
+ *  B - L (L^T X)).  The server also keeps L^T and its inverted blocks (about
+ *  twice the memory of a triangular factor); n^2 k flops count twice.  With
+ *  TRSM_F32 their block size is at most 512 (A's squared conditioning eats
+ *  the binary32 margin of larger inverted blocks, costing corrections).
  * trsm_serve_submit(srv, l_id, B, k, ldb, X, ldx, &ticket): never blocks.
  *  B (read) and X (written) are caller-owned binary64 device matrices (n x k,
- *  row-major) that must stay valid until the ticket is DONE or ERROR.  The
- *  request waits until its workspace (32 n k bytes with k rounded up to 4;
- *  44 n k on a Cholesky factor) fits the budget
- *  and a slot is free, then joins the next batch, which runs on one of the
- *  server's streams while earlier batches may still be running.  Each
- *  request is solved with binary32 sweeps and one refinement step with a
- *  binary64 residual; its result does not depend on the other requests.
- *  A request that can never fit fails with TRSM_ENOMEM.
- * trsm_serve_poll(srv, ticket, &state, &latency_us): never blocks.  A DONE
- *  or ERROR ticket is reported once (then forgotten); latency is submit ->
- *  completion observed by the worker, in microseconds.  Returns the
- *  request's error status for ERROR.
+ *  row-major, not overlapping) that must stay valid until the ticket is
+ *  finished.  The request waits until its workspace (trsm_serve_request_bytes)
+ *  fits the budget and a slot is free, then joins the next batch,
+ *  which runs on one of the server's streams while earlier batches may still
+ *  be running; between passes it rejoins the batches with the newest
+ *  arrivals.  A request that can never fit fails with TRSM_ENOMEM.
+ * trsm_serve_request_bytes(srv, l_id, k, &bytes): the device bytes a request
+ *  of k columns on factor l_id holds while admitted (its buffers above, its
+ *  norm partials and the split-K scratch of its skinny products: at most
+ *  max(64 n k, 4 MiB) bytes more), for sizing hbm_budget.  Host only.
+ * trsm_serve_poll(srv, ticket, &state, &info): never blocks.  info (may be
+ *  null) receives the request's trsm_info once it is DONE: corrections
+ *  applied, converged flag, berr and corr of its last pass, and the first
+ *  correction's corr as unrefined_error (-1 where not measured).  Returns
+ *  TRSM_OK while PENDING or RUNNING; for a finished ticket (reported once,
+ *  then forgotten) the request's status: TRSM_OK, TRSM_ENOTCONVERGED (state
+ *  DONE, X holds the last iterate), or an error with state ERROR (X
+ *  undefined).  TRSM_EINVAL and TRSM_REQ_UNKNOWN for an unknown ticket.
  * trsm_server_stats / trsm_server_reset_stats: counters, p50/p99/mean
- *  latency of completed requests, n^2 k flops completed (2 n^2 k for a
- *  Cholesky factor), memory in use.
+ *  latency (submit to completion seen by the worker) of finished requests,
+ *  n^2 k flops of finished requests (2 n^2 k for a Cholesky factor), memory in
+ *  use.
  * trsm_server_destroy: waits for queued and in-flight work, frees everything.
  */
 typedef enum trsm_req_state {
@@ -376,6 +416,8 @@ typedef enum trsm_req_state {
 
 typedef struct trsm_serve_stats {
   uint64_t submitted, completed, failed, batches;
+  uint64_t unconverged;    /* completed requests that ended with TRSM_ENOTCONVERGED */
+  uint64_t passes;         /* request passes run (a request's first pass counts too) */
   double p50_us, p99_us, mean_us;
   double flops_done;       /* sum of n^2 k over completed requests (2 n^2 k on
                               Cholesky factors) */
@@ -384,18 +426,27 @@ typedef struct trsm_serve_stats {
   int32_t queue_depth, in_flight, max_in_flight, factors;
 } trsm_serve_stats;
 
+typedef struct trsm_server_options {
+  int64_t n0;              /* 0: min(next power of two >= n, 4096) per factor */
+  double tolerance;        /* 0: sqrt(n) 2^-53 per factor */
+  int32_t max_corrections; /* 0: 10 */
+  int32_t reserved;        /* must be 0 */
+} trsm_server_options;
+
 typedef struct trsm_server_s* trsm_server_t;
 
-trsm_status trsm_server_create(size_t hbm_budget, int32_t max_slots, int64_t n0,
-                               trsm_server_t* out);
+trsm_status trsm_server_create(size_t hbm_budget, int32_t max_slots, trsm_server_t* out);
+trsm_status trsm_server_create_ex(size_t hbm_budget, int32_t max_slots,
+                                  const trsm_server_options* options, trsm_server_t* out);
 trsm_status trsm_server_register_L(trsm_server_t srv, const double* L, int64_t n, int64_t ldl,
-                                   int32_t* l_id);
+                                   trsm_precision prec, int32_t* l_id);
 trsm_status trsm_server_register_chol(trsm_server_t srv, const double* L, int64_t n, int64_t ldl,
-                                      int32_t* l_id);
+                                      trsm_precision prec, int32_t* l_id);
 trsm_status trsm_serve_submit(trsm_server_t srv, int32_t l_id, const double* B, int64_t k,
                               int64_t ldb, double* X, int64_t ldx, uint64_t* ticket);
+trsm_status trsm_serve_request_bytes(trsm_server_t srv, int32_t l_id, int64_t k, size_t* bytes);
 trsm_status trsm_serve_poll(trsm_server_t srv, uint64_t ticket, trsm_req_state* state,
-                            double* latency_us);
+                            trsm_info* info);
 trsm_status trsm_server_stats(trsm_server_t srv, trsm_serve_stats* stats);
 trsm_status trsm_server_reset_stats(trsm_server_t srv);
 trsm_status trsm_server_destroy(trsm_server_t srv);

@@ -14,21 +14,102 @@ namespace trsm {
 
 namespace {
 
-// Grouped elementwise kernel: entry e owns workgroups [start[e], start[e+1]),
-// each workgroup converts kEwChunk consecutive elements (row-major order) of
-// its matrix.
-__global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restrict__ entries,
-                                                         const int* __restrict__ start, int n) {
-  const int b = blockIdx.x;
+// Index of the entry that owns workgroup b (start[] is the prefix array).
+__device__ __forceinline__ int owner_of(const int* __restrict__ start, int n, int b) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (start[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
+  return lo;
+}
+
+// A sum of squares kept as s * 4^e with s in a safe range, so that it does
+// not overflow or underflow whatever the magnitudes summed (the exponent is
+// raised to the largest exponent seen and smaller terms are scaled by exact
+// powers of two).  Not-finite terms make s not finite.
+struct Sq {
+  double s;
+  int e;
+};
+constexpr int kSqEmpty = -4000;
+
+__device__ __forceinline__ void sq_add(Sq& a, double x) {
+  const double ax = fabs(x);
+  if (ax == 0.0) return;
+  if (!(ax <= 1.7976931348623157e308)) {
+    a.s += ax;   // infinity or NaN
+    return;
+  }
+  const int e = ilogb(ax);
+  if (e > a.e) {
+    a.s = ldexp(a.s, 2 * (a.e - e));
+    a.e = e;
+  }
+  const double y = ldexp(ax, -a.e);
+  a.s += y * y;
+}
+
+__device__ __forceinline__ Sq sq_merge(Sq a, Sq b) {
+  const int e = max(a.e, b.e);
+  return Sq{ldexp(a.s, 2 * (a.e - e)) + ldexp(b.s, 2 * (b.e - e)), e};
+}
+
+// Merge over the 64 lanes of a wavefront (butterfly: a fixed order).
+__device__ __forceinline__ Sq wave_sq(Sq v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Sq w{__shfl_xor(v.s, o, 64), __shfl_xor(v.e, o, 64)};
+    v = sq_merge(v, w);
+  }
+  return v;
+}
+
+// The sum of quantity q over an entry's parts (partial layout of RedEntry),
+// by one wavefront in a fixed order.
+__device__ __forceinline__ Sq parts_sq(const double* part, int nparts, int q, int lane) {
+  Sq v{0.0, kSqEmpty};
+  for (int p = lane; p < nparts; p += 64)
+    v = sq_merge(v, Sq{part[kPartStride * p + q], (int)part[kPartStride * p + 3 + q]});
+  return wave_sq(v);
+}
+
+// 2^-e for a sum of squares whose square root lies below 2^e (e clamped to
+// +-1000); 1 when the sum is zero or not finite.
+__device__ __forceinline__ double pow2_inv_scale(Sq v) {
+  if (!(v.s > 0.0) || !(v.s <= 1.7976931348623157e308)) return 1.0;
+  int e1;
+  (void)frexp(sqrt(v.s), &e1);
+  const int e = max(-1000, min(1000, v.e + e1));
+  return ldexp(1.0, -e);
+}
+
+// Grouped elementwise kernel: entry e owns workgroups [start[e], start[e+1]),
+// each workgroup converts kEwChunk consecutive elements (row-major order) of
+// its matrix.
+__global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restrict__ entries,
+                                                         const int* __restrict__ start, int n) {
+  const int b = blockIdx.x;
+  const int lo = owner_of(start, n, b);
   const EwEntry& e = entries[lo];
   const int64_t total = (int64_t)e.rows * e.cols;
   const int64_t base = (int64_t)(b - start[lo]) * kEwChunk;
+  // scaled ops: the scale is uniform over the entry (every workgroup of it
+  // derives the same value from the same partial sums, in the same order)
+  double sc = 1.0;
+  if (e.op == EW_F64_TO_F32_PS) {
+    __shared__ double sh;
+    if (threadIdx.x < 64) {
+      const Sq v = parts_sq(e.part, e.nparts, 0, threadIdx.x);
+      if (threadIdx.x == 0) sh = pow2_inv_scale(v);
+    }
+    __syncthreads();
+    sc = sh;
+    if (b == start[lo] && threadIdx.x == 0) *e.sc = sc;
+  } else if (e.op == EW_F32_TO_F64_SET_SC || e.op == EW_F32_TO_F64_ADD_SC) {
+    sc = 1.0 / *e.sc;   // exact: a power of two
+  }
   for (int64_t i = base + threadIdx.x; i < min(total, base + kEwChunk); i += 256) {
     const int64_t r = i / e.cols, c = i % e.cols;
     const bool pad = c >= e.valid_cols;
@@ -51,6 +132,23 @@ __global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restri
         static_cast<double*>(e.dst)[r * e.ldd + c] =
             pad ? 0.0 : e.scale * static_cast<const double*>(e.src)[r * e.lds + c];
         break;
+      case EW_F64_TO_F32_PS:
+        static_cast<float*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0f : static_cast<float>(sc * static_cast<const double*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F32_TO_F64_SET_SC:
+        static_cast<double*>(e.dst)[r * e.ldd + c] =
+            pad ? 0.0 : sc * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F32_TO_F64_ADD_SC:
+        if (!pad)
+          static_cast<double*>(e.dst)[r * e.ldd + c] +=
+              sc * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
+        break;
+      case EW_F64_ADD:
+        if (!pad)
+          static_cast<double*>(e.dst)[r * e.ldd + c] += static_cast<const double*>(e.src)[r * e.lds + c];
+        break;
       default:
         static_cast<float*>(e.dst)[r * e.ldd + c] =
             pad ? 0.0f : static_cast<float>(e.scale) * static_cast<const float*>(e.src)[r * e.lds + c];
@@ -59,7 +157,110 @@ __global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restri
   }
 }
 
+// Grouped reductions (see RedOp): entry e owns workgroups [start[e],
+// start[e+1]), one per chunk; the three partial sums of a chunk are merged
+// per wavefront, then over the four wavefronts in order.
+__global__ __launch_bounds__(256) void grouped_red_kernel(const RedEntry* __restrict__ entries,
+                                                          const int* __restrict__ start, int n) {
+  const int b = blockIdx.x;
+  const int lo = owner_of(start, n, b);
+  const RedEntry& e = entries[lo];
+  const int p = b - start[lo];
+  const int64_t total = (int64_t)e.rows * e.cols;
+  const int64_t base = (int64_t)p * e.chunk;
+  const int64_t end = min(total, base + e.chunk);
+  Sq s0{0.0, kSqEmpty}, s1{0.0, kSqEmpty}, s2{0.0, kSqEmpty};
+  for (int64_t i = base + threadIdx.x; i < end; i += 256) {
+    const int64_t r = i / e.cols, c = i % e.cols;
+    if (e.op == RD_LOAD) {
+      const double v = (c < e.valid_cols && r < e.valid_rows) ? e.a[r * e.lda + c] : 0.0;
+      e.b[r * e.ldb + c] = v;
+      sq_add(s0, v);
+    } else if (e.op == RD_RES) {
+      sq_add(s0, e.a[r * e.lda + c]);
+    } else {
+      const double x = e.b[r * e.ldb + c];
+      sq_add(s0, e.a[r * e.lda + c]);
+      sq_add(s1, x);
+      if (e.d)
+        sq_add(s2, e.d_f64 ? static_cast<const double*>(e.d)[r * e.ldd + c]
+                           : static_cast<double>(static_cast<const float*>(e.d)[r * e.ldd + c]));
+      if (c < e.valid_cols && r < e.valid_rows) e.xo[r * e.ldxo + c] = x;
+    }
+  }
+  __shared__ double rs[4][3];
+  __shared__ int re[4][3];
+  s0 = wave_sq(s0);
+  s1 = wave_sq(s1);
+  s2 = wave_sq(s2);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rs[w][0] = s0.s; re[w][0] = s0.e;
+    rs[w][1] = s1.s; re[w][1] = s1.e;
+    rs[w][2] = s2.s; re[w][2] = s2.e;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    Sq v{rs[0][q], re[0][q]};
+    for (int j = 1; j < 4; ++j) v = sq_merge(v, Sq{rs[j][q], re[j][q]});
+    e.part[kPartStride * p + q] = v.s;
+    e.part[kPartStride * p + 3 + q] = (double)v.e;
+  }
+}
+
+// Final sums: one wavefront per entry.
+__global__ __launch_bounds__(64) void grouped_fin_kernel(const FinEntry* __restrict__ entries) {
+  const FinEntry& e = entries[blockIdx.x];
+  const Sq s0 = parts_sq(e.part, e.nparts, 0, threadIdx.x);
+  const Sq s1 = parts_sq(e.part, e.nparts, 1, threadIdx.x);
+  const Sq s2 = parts_sq(e.part, e.nparts, 2, threadIdx.x);
+  if (threadIdx.x == 0) {
+    // a correction computed in scaled units: divide its sum by sc^2
+    const int es = e.sc ? ilogb(*e.sc) : 0;
+    e.out[0] = s0.s; e.out[1] = (double)s0.e;
+    e.out[2] = s1.s; e.out[3] = (double)s1.e;
+    e.out[4] = s2.s; e.out[5] = (double)(s2.e - es);
+  }
+}
+
+// Split-K finish of grouped products: the fixed-order sum of each element's
+// ksplit partial sums, then the product's epilogue.  Entry e owns workgroups
+// [start[e], start[e+1]), kFinChunk elements each.
+constexpr int kFinChunk = 2048;
+template <typename T>
+__global__ __launch_bounds__(256) void grouped_split_finish(
+    const GemmParams<T, T, T, float>* __restrict__ entries, const int* __restrict__ start,
+    int n) {
+  using Acc = typename Mfma<T>::Acc;
+  using Epi = EpiType<T, T, T>;
+  const int b = blockIdx.x;
+  const int lo = owner_of(start, n, b);
+  const GemmParams<T, T, T, float>& p = entries[lo];
+  const int64_t MN = (int64_t)p.M * p.N;
+  const int64_t base = (int64_t)(b - start[lo]) * kFinChunk;
+  Epi alpha = static_cast<Epi>(p.alpha);
+  if (p.ascale) alpha *= static_cast<Epi>(*p.ascale);
+  const Epi beta = static_cast<Epi>(p.beta);
+  const bool use_beta = (p.flags & G_BETA) && p.Cin;
+  const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
+  const Acc* __restrict__ P = static_cast<const Acc*>(p.part);
+  for (int64_t e = base + threadIdx.x; e < min(MN, base + kFinChunk); e += 256) {
+    const int row = (int)(e / p.N), col = (int)(e - (int64_t)row * p.N);
+    if ((p.flags & G_C_LOWER) && col > row) continue;
+    Acc v = P[e];
+    for (int t = 1; t < p.ksplit; ++t) v += P[t * MN + e];
+    const Epi rs = use_rs ? static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]) : Epi(1);
+    epi_store(p, p.Cout, p.Cin, row, col, static_cast<Epi>(v), alpha, beta, use_beta, rs);
+  }
+}
+
 constexpr int kBM = 128, kBN = 128;
+// Aligned products of at most kNarrowN columns (skinny right-hand sides) use
+// 128 x 32 tiles of four waves stacked along M: a quarter of the matrix-core
+// work of a 128 x 128 tile on padding.  The k order of every element is the
+// same as with the wide tiles, so the bits are too.
+constexpr int kNarrowN = 32;
 
 // Waits of the persistent sweep give up (and set the error word) after this
 // many polls of about a microsecond; by construction a wait always ends long
@@ -196,42 +397,77 @@ size_t LaunchList::append(const T* data, size_t n) {
 }
 
 namespace {
-template <typename P>
-std::vector<int> gemm_starts(const std::vector<P>& e, int* total) {
-  std::vector<int> st(e.size() + 1, 0);
-  for (size_t i = 0; i < e.size(); ++i) {
-    const int64_t tiles = gemm_wgs(e[i].M, e[i].N, e[i].K, e[i].flags, kBM, kBN);
-    st[i + 1] = st[i] + (int)tiles;
-  }
-  *total = st.back();
-  return st;
+// Split of one grouped product (see SweepItem::part): products with at most
+// half a round of 128 x 128 workgroups cut K into up to kSplitMax slices of
+// at least kSplitMinChunks chunks each, as far as the scratch holds them.
+template <typename T>
+int grouped_ksplit(const GemmParams<T, T, T, float>& p) {
+  if (!p.part) return 1;
+  return grouped_split_slices(p.M, p.N, p.K, p.flags, p.part_bytes, (int)sizeof(T));
 }
 }  // namespace
 
-void LaunchList::add_gemm64(const std::vector<GemmP64>& entries) {
+int grouped_split_slices(int M, int N, int K, uint32_t flags, int64_t part_bytes, int elem) {
+  if (M <= 0 || N <= 0) return 1;
+  const int64_t tiles = gemm_wgs(M, N, K, flags, kBM, kBN);
+  if (2 * tiles > kSplitTarget) return 1;
+  const int64_t nck = (K + 128 / elem - 1) / (128 / elem);   // chunks of 128 bytes
+  int64_t S = std::min<int64_t>(kSplitTarget / tiles, nck / kSplitMinChunks);
+  S = std::min<int64_t>(S, kSplitMax);
+  S = std::min<int64_t>(S, part_bytes / ((int64_t)M * N * elem));   // binary32/64 partials
+  return S > 1 ? (int)S : 1;
+}
+
+template <typename P>
+void LaunchList::add_gemm(int kind, int split_kind, std::vector<P> entries) {
   if (entries.empty()) return;
-  Phase ph{};
-  ph.kind = PH_GEMM_F64;
-  ph.count = (int)entries.size();
-  ph.aligned = true;
-  for (const auto& e : entries) ph.aligned &= gemm_aligned<double, kBM, kBN, false>(e);
-  std::vector<int> st = gemm_starts(entries, &ph.total);
-  ph.entries_off = append(entries.data(), entries.size());
-  ph.start_off = append(st.data(), st.size());
-  if (ph.total > 0) phases_.push_back(ph);
+  using T = typename std::remove_const<typename std::remove_pointer<decltype(P::A)>::type>::type;
+  // sub-launches: aligned narrow, aligned wide, unaligned (wide tiles)
+  std::vector<P> sub[3];
+  std::vector<P> split;
+  for (P& e : entries) {
+    e.ksplit = grouped_ksplit<T>(e);
+    if (e.ksplit > 1) split.push_back(e);
+    const bool al = gemm_aligned<T, kBM, kBN, false>(e);
+    sub[!al ? 2 : (e.N <= kNarrowN ? 0 : 1)].push_back(e);
+  }
+  for (int v = 0; v < 3; ++v) {
+    if (sub[v].empty()) continue;
+    Phase ph{};
+    ph.kind = kind;
+    ph.count = (int)sub[v].size();
+    ph.aligned = v < 2;
+    ph.narrow = v == 0;
+    const int bn = ph.narrow ? kNarrowN : kBN;
+    std::vector<int> st(sub[v].size() + 1, 0);
+    for (size_t i = 0; i < sub[v].size(); ++i) {
+      const P& e = sub[v][i];
+      st[i + 1] = st[i] + gemm_wgs(e.M, e.N, e.K, e.flags, kBM, bn) * e.ksplit;
+    }
+    ph.total = st.back();
+    ph.entries_off = append(sub[v].data(), sub[v].size());
+    ph.start_off = append(st.data(), st.size());
+    if (ph.total > 0) phases_.push_back(ph);
+  }
+  if (split.empty()) return;
+  Phase fin{};
+  fin.kind = split_kind;
+  fin.count = (int)split.size();
+  std::vector<int> fs(split.size() + 1, 0);
+  for (size_t i = 0; i < split.size(); ++i)
+    fs[i + 1] = fs[i] + (int)ceil_div((int64_t)split[i].M * split[i].N, kFinChunk);
+  fin.total = fs.back();
+  fin.entries_off = append(split.data(), split.size());
+  fin.start_off = append(fs.data(), fs.size());
+  phases_.push_back(fin);
+}
+
+void LaunchList::add_gemm64(const std::vector<GemmP64>& entries) {
+  add_gemm(PH_GEMM_F64, PH_SPLIT_F64, entries);
 }
 
 void LaunchList::add_gemm32(const std::vector<GemmP32>& entries) {
-  if (entries.empty()) return;
-  Phase ph{};
-  ph.kind = PH_GEMM_F32;
-  ph.count = (int)entries.size();
-  ph.aligned = true;
-  for (const auto& e : entries) ph.aligned &= gemm_aligned<float, kBM, kBN, false>(e);
-  std::vector<int> st = gemm_starts(entries, &ph.total);
-  ph.entries_off = append(entries.data(), entries.size());
-  ph.start_off = append(st.data(), st.size());
-  if (ph.total > 0) phases_.push_back(ph);
+  add_gemm(PH_GEMM_F32, PH_SPLIT_F32, entries);
 }
 
 void LaunchList::add_ew(const std::vector<EwEntry>& entries) {
@@ -247,6 +483,37 @@ void LaunchList::add_ew(const std::vector<EwEntry>& entries) {
   ph.entries_off = append(entries.data(), entries.size());
   ph.start_off = append(st.data(), st.size());
   if (ph.total > 0) phases_.push_back(ph);
+}
+
+void red_split(int64_t rows, int64_t cols, int* chunk, int* nparts) {
+  const int64_t total = rows * cols;
+  int64_t c = std::max<int64_t>(kEwChunk, ceil_div(ceil_div(total, kRedMaxParts), 256) * 256);
+  *chunk = (int)c;
+  *nparts = (int)std::max<int64_t>(1, ceil_div(total, c));
+}
+
+void LaunchList::add_red(const std::vector<RedEntry>& entries) {
+  if (entries.empty()) return;
+  Phase ph{};
+  ph.kind = PH_RED;
+  ph.count = (int)entries.size();
+  std::vector<int> st(entries.size() + 1, 0);
+  for (size_t i = 0; i < entries.size(); ++i) st[i + 1] = st[i] + entries[i].nparts;
+  ph.total = st.back();
+  ph.entries_off = append(entries.data(), entries.size());
+  ph.start_off = append(st.data(), st.size());
+  if (ph.total > 0) phases_.push_back(ph);
+}
+
+void LaunchList::add_fin(const std::vector<FinEntry>& entries) {
+  if (entries.empty()) return;
+  Phase ph{};
+  ph.kind = PH_FIN;
+  ph.count = (int)entries.size();
+  ph.total = ph.count;
+  ph.entries_off = append(entries.data(), entries.size());
+  ph.start_off = ph.entries_off;
+  phases_.push_back(ph);
 }
 
 template <typename T>
@@ -288,7 +555,10 @@ hipError_t LaunchList::run(const void* dev, hipStream_t s) const {
     dim3 grid((unsigned)ph.total);
     if (ph.kind == PH_GEMM_F64) {
       const GemmP64* e = reinterpret_cast<const GemmP64*>(base + ph.entries_off);
-      if (ph.aligned)
+      if (ph.narrow)
+        gemm_grouped_kernel<double, double, double, float, kBM, kNarrowN, 4, 1, false, true>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+      else if (ph.aligned)
         gemm_grouped_kernel<double, double, double, float, kBM, kBN, 2, 2, false, true>
             <<<grid, 256, 0, s>>>(e, st, ph.count);
       else
@@ -296,12 +566,27 @@ hipError_t LaunchList::run(const void* dev, hipStream_t s) const {
             <<<grid, 256, 0, s>>>(e, st, ph.count);
     } else if (ph.kind == PH_GEMM_F32) {
       const GemmP32* e = reinterpret_cast<const GemmP32*>(base + ph.entries_off);
-      if (ph.aligned)
+      if (ph.narrow)
+        gemm_grouped_kernel<float, float, float, float, kBM, kNarrowN, 4, 1, false, true>
+            <<<grid, 256, 0, s>>>(e, st, ph.count);
+      else if (ph.aligned)
         gemm_grouped_kernel<float, float, float, float, kBM, kBN, 2, 2, false, true>
             <<<grid, 256, 0, s>>>(e, st, ph.count);
       else
         gemm_grouped_kernel<float, float, float, float, kBM, kBN, 2, 2, false, false>
             <<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else if (ph.kind == PH_SPLIT_F64) {
+      const GemmP64* e = reinterpret_cast<const GemmP64*>(base + ph.entries_off);
+      grouped_split_finish<double><<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else if (ph.kind == PH_SPLIT_F32) {
+      const GemmP32* e = reinterpret_cast<const GemmP32*>(base + ph.entries_off);
+      grouped_split_finish<float><<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else if (ph.kind == PH_RED) {
+      const RedEntry* e = reinterpret_cast<const RedEntry*>(base + ph.entries_off);
+      grouped_red_kernel<<<grid, 256, 0, s>>>(e, st, ph.count);
+    } else if (ph.kind == PH_FIN) {
+      const FinEntry* e = reinterpret_cast<const FinEntry*>(base + ph.entries_off);
+      grouped_fin_kernel<<<grid, 64, 0, s>>>(e);
     } else {
       const EwEntry* e = reinterpret_cast<const EwEntry*>(base + ph.entries_off);
       grouped_ew_kernel<<<grid, 256, 0, s>>>(e, st, ph.count);
@@ -331,6 +616,7 @@ void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items) {
       p.Cout = it.X + r0 * it.ldx; p.ldco = it.ldx;
       p.M = (int)sz; p.N = (int)it.k; p.K = (int)sz;
       p.flags = G_A_LOWER | G_A_ZERO_UPPER;
+      p.part = it.part; p.part_bytes = it.part_bytes;
       trmm.push_back(p);
       if (i + 1 < m) {
         // B'(T_{i+1}) = B'(T_{i+1}) - L(T_{i+1}, S_i) X(S_i)
@@ -344,6 +630,7 @@ void record_sweep(LaunchList& list, const std::vector<SweepItem<T>>& items) {
         q.M = (int)(it.n - t0); q.N = (int)it.k; q.K = (int)sz;
         q.alpha = -1.0; q.beta = 1.0;
         q.flags = G_BETA;
+        q.part = it.part; q.part_bytes = it.part_bytes;
         upd.push_back(q);
       }
     }
@@ -380,6 +667,7 @@ void record_sweep_back(LaunchList& list, const std::vector<SweepItem<T>>& items)
       p.Cout = it.X + r0 * it.ldx; p.ldco = it.ldx;
       p.M = (int)sz; p.N = (int)it.k; p.K = (int)sz;
       p.flags = G_A_UPPER;
+      p.part = it.part; p.part_bytes = it.part_bytes;
       diag.push_back(p);
       if (i > 0) {
         // B'(0:r0) = B'(0:r0) - U(0:r0, S_i) X(S_i)
@@ -392,6 +680,7 @@ void record_sweep_back(LaunchList& list, const std::vector<SweepItem<T>>& items)
         q.M = (int)r0; q.N = (int)it.k; q.K = (int)sz;
         q.alpha = -1.0; q.beta = 1.0;
         q.flags = G_BETA;
+        q.part = it.part; q.part_bytes = it.part_bytes;
         upd.push_back(q);
       }
     }

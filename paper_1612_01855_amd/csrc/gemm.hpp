@@ -800,7 +800,7 @@ __global__ __launch_bounds__(256) void gemm_splitk_finish(GemmParams<TIn, TCin, 
 
 // Grouped launch: many independent products of one element type in one
 // grid.  Entry e owns workgroups [tile_start[e], tile_start[e+1]); within an
-// entry the workgroups cover batch x tiles as in gemm_kernel.
+// entry the workgroups cover ksplit x tiles (K slice, then tile).
 template <typename TIn, typename TCin, typename TCout, typename TC2,
           int BM, int BN, int WGM, int WGN, bool BKMAJOR, bool ALIGNED>
 __global__ __launch_bounds__(WGM * WGN * 64, 2)
@@ -816,7 +816,7 @@ void gemm_grouped_kernel(const GemmParams<TIn, TCin, TCout, TC2>* __restrict__ e
   const GemmParams<TIn, TCin, TCout, TC2>& p = entries[lo];
   const int tiles = gemm_wgs(p.M, p.N, p.K, p.flags, BM, BN);
   const int local = b - tile_start[lo];
-  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, local / tiles, 0,
+  gemm_tile<TIn, TCin, TCout, TC2, BM, BN, WGM, WGN, BKMAJOR, ALIGNED>(p, 0, local / tiles,
                                                                       local % tiles, tiles);
 }
 

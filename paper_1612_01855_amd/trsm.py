@@ -64,12 +64,18 @@ class BatchItem(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("unconverged", ctypes.c_uint64), ("passes", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("flops_done", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("hbm_budget", ctypes.c_size_t),
                 ("hbm_in_use", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t),
                 ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32),
                 ("max_in_flight", ctypes.c_int32), ("factors", ctypes.c_int32)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("tolerance", ctypes.c_double),
+                ("max_corrections", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 # trsm_req_state
@@ -82,7 +88,8 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
            "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
-           "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_poll",
+           "trsm_server_create_ex", "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_request_bytes",
+           "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy",
            "trsm_chol_sizes", "trsm_chol_factor", "trsm_chol_check",
            "trsm_lu_sizes", "trsm_lu_factor", "trsm_lu_check"]
@@ -156,17 +163,24 @@ def _load():
     lib.trsm_batch_check.restype = i32
     lib.trsm_batch_destroy.argtypes = [vp]
     lib.trsm_batch_destroy.restype = i32
-    lib.trsm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, i64, ctypes.POINTER(vp)]
+    lib.trsm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
     lib.trsm_server_create.restype = i32
-    lib.trsm_server_register_L.argtypes = [vp, vp, i64, i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.trsm_server_create_ex.argtypes = [ctypes.c_size_t, ctypes.c_int32,
+                                          ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
+    lib.trsm_server_create_ex.restype = i32
+    lib.trsm_server_register_L.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(ctypes.c_int32)]
     lib.trsm_server_register_L.restype = i32
-    lib.trsm_server_register_chol.argtypes = [vp, vp, i64, i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.trsm_server_register_chol.argtypes = [vp, vp, i64, i64, i32,
+                                              ctypes.POINTER(ctypes.c_int32)]
     lib.trsm_server_register_chol.restype = i32
     lib.trsm_serve_submit.argtypes = [vp, ctypes.c_int32, vp, i64, i64, vp, i64,
                                       ctypes.POINTER(ctypes.c_uint64)]
     lib.trsm_serve_submit.restype = i32
+    lib.trsm_serve_request_bytes.argtypes = [vp, ctypes.c_int32, i64,
+                                             ctypes.POINTER(ctypes.c_size_t)]
+    lib.trsm_serve_request_bytes.restype = i32
     lib.trsm_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32),
-                                    ctypes.POINTER(ctypes.c_double)]
+                                    ctypes.POINTER(Info)]
     lib.trsm_serve_poll.restype = i32
     lib.trsm_server_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     lib.trsm_server_stats.restype = i32
@@ -322,25 +336,33 @@ def trsm_batch_destroy(batch: int) -> None:
     _check(_lib.trsm_batch_destroy(batch), "trsm_batch_destroy")
 
 
-def trsm_server_create(hbm_budget: int, max_slots: int = 64, n0: int = 128) -> int:
+def trsm_server_create(hbm_budget: int, max_slots: int = 64, n0: int = 0,
+                       tolerance: float = 0.0, max_corrections: int = 0) -> int:
+    """A server; n0, tolerance, max_corrections = 0 keep the library's defaults."""
     h = ctypes.c_void_p()
-    _check(_lib.trsm_server_create(hbm_budget, max_slots, n0, ctypes.byref(h)),
-           "trsm_server_create")
+    if n0 or tolerance or max_corrections:
+        opt = ServerOptions(n0, tolerance, max_corrections, 0)
+        _check(_lib.trsm_server_create_ex(hbm_budget, max_slots, ctypes.byref(opt),
+                                          ctypes.byref(h)), "trsm_server_create_ex")
+    else:
+        _check(_lib.trsm_server_create(hbm_budget, max_slots, ctypes.byref(h)),
+               "trsm_server_create")
     return h.value
 
 
-def trsm_server_register_L(srv: int, L: int, n: int, ldl: int) -> int:
+def trsm_server_register_L(srv: int, L: int, n: int, ldl: int, precision: str = "f32") -> int:
     lid = ctypes.c_int32()
-    _check(_lib.trsm_server_register_L(srv, L, n, ldl, ctypes.byref(lid)),
+    _check(_lib.trsm_server_register_L(srv, L, n, ldl, PRECISIONS[precision], ctypes.byref(lid)),
            "trsm_server_register_L")
     return lid.value
 
 
-def trsm_server_register_chol(server: int, L: int, n: int, ldl: int) -> int:
+def trsm_server_register_chol(server: int, L: int, n: int, ldl: int,
+                              precision: str = "f32") -> int:
     """Register L as the Cholesky factor of A = L L^T: requests solve A X = B."""
     lid = ctypes.c_int32()
-    _check(_lib.trsm_server_register_chol(server, L, n, ldl, ctypes.byref(lid)),
-           "trsm_server_register_chol")
+    _check(_lib.trsm_server_register_chol(server, L, n, ldl, PRECISIONS[precision],
+                                          ctypes.byref(lid)), "trsm_server_register_chol")
     return lid.value
 
 
@@ -351,11 +373,20 @@ def trsm_serve_submit(srv: int, l_id: int, B: int, k: int, ldb: int, X: int, ldx
     return t.value
 
 
+def trsm_serve_request_bytes(srv: int, l_id: int, k: int) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.trsm_serve_request_bytes(srv, l_id, k, ctypes.byref(b)),
+           "trsm_serve_request_bytes")
+    return b.value
+
+
 def trsm_serve_poll(srv: int, ticket: int):
-    """(state, status, latency_us); a finished ticket is reported once."""
-    st, lat = ctypes.c_int(), ctypes.c_double()
-    status = _lib.trsm_serve_poll(srv, ticket, ctypes.byref(st), ctypes.byref(lat))
-    return st.value, status, lat.value
+    """(state, status, info): info is the request's Info once it is finished
+    (else None); a finished ticket is reported once."""
+    st, info = ctypes.c_int(), Info()
+    status = _lib.trsm_serve_poll(srv, ticket, ctypes.byref(st), ctypes.byref(info))
+    done = st.value in (REQ_DONE, REQ_ERROR)
+    return st.value, status, info if done else None
 
 
 def trsm_server_stats(srv: int) -> ServeStats:

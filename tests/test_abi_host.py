@@ -177,12 +177,31 @@ def test_batch_create_validation_and_workspace(T):
 def test_server_argument_validation_without_gpu(T):
     lib = T._lib
     h = ctypes.c_void_p()
-    assert lib.trsm_server_create(1 << 30, 0, 128, ctypes.byref(h)) == T.EINVAL   # no slots
-    assert lib.trsm_server_create(1 << 30, 8, 96, ctypes.byref(h)) == T.EINVAL    # n0
-    assert lib.trsm_server_create(1 << 10, 8, 128, ctypes.byref(h)) == T.EINVAL   # tiny budget
-    assert lib.trsm_server_create(1 << 30, 8, 128, None) == T.EINVAL
+    assert lib.trsm_server_create(1 << 30, 0, ctypes.byref(h)) == T.EINVAL   # no slots
+    assert lib.trsm_server_create(1 << 10, 8, ctypes.byref(h)) == T.EINVAL   # tiny budget
+    assert lib.trsm_server_create(1 << 30, 8, None) == T.EINVAL
+    bad = [T.ServerOptions(96, 0.0, 0, 0),      # n0 not a power of two
+           T.ServerOptions(-64, 0.0, 0, 0),
+           T.ServerOptions(0, -1.0, 0, 0),      # negative tolerance
+           T.ServerOptions(0, float("nan"), 0, 0),
+           T.ServerOptions(0, 0.0, -1, 0),      # correction cap out of range
+           T.ServerOptions(0, 0.0, 51, 0),
+           T.ServerOptions(0, 0.0, 0, 1)]       # reserved field set
+    for o in bad:
+        assert lib.trsm_server_create_ex(1 << 30, 8, ctypes.byref(o), ctypes.byref(h)) == T.EINVAL
+        assert h.value is None
+    assert lib.trsm_server_create_ex(1 << 30, 8, None, ctypes.byref(h)) == T.EINVAL
     st = ctypes.c_int()
     assert lib.trsm_serve_poll(None, 1, ctypes.byref(st), None) == T.EINVAL
+    info = T.Info()
+    assert lib.trsm_serve_poll(None, 1, ctypes.byref(st), ctypes.byref(info)) == T.EINVAL
+    lid = ctypes.c_int32()
+    assert lib.trsm_server_register_L(None, None, 10, 10, T.F32, ctypes.byref(lid)) == T.EINVAL
+    assert lib.trsm_server_register_chol(None, None, 10, 10, T.F64, ctypes.byref(lid)) == T.EINVAL
+    t = ctypes.c_uint64()
+    assert lib.trsm_serve_submit(None, 0, None, 1, 1, None, 1, ctypes.byref(t)) == T.EINVAL
+    assert lib.trsm_server_stats(None, None) == T.EINVAL
+    assert lib.trsm_server_reset_stats(None) == T.EINVAL
     assert lib.trsm_server_destroy(None) == T.OK
 
 
