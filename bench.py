@@ -612,15 +612,22 @@ def main():
         f"invert {step_stats['invert_ms_median']} ms, solve {step_stats['solve_ms_median']} ms")
 
     workload = f"trsm_{args.precision}_n{n}_k{k}"
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    # achieved: the step's n^2 k flops (the metric's count; the inversion's
+    # extra flops are not credited) over the summed durations of all of the
+    # step's product launches (inversion and sweep), timed with hipEvents on
+    # the solve stream
+    launches_step = max(launches // args.steps, 1)
+    gemm_ms_step = gemm_ms / args.steps
+    achieved = flops_step / (gemm_ms_step * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     peak = PEAK[args.precision]
     traffic = traffic_from_profiles(workload, info.n0, bool(info.flags & T.FLAG_LARGE_TILES))
     roofline = {"bound": "mfma", "kernel": "gemm_kernel (all product launches of a step)",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "launches_per_step": launches // args.steps,
+                "launches_per_step": launches_step,
                 "avg_launch_ms": round(gemm_ms / max(launches, 1), 4),
-                "algorithmic_flops_per_launch": gemm_flops / max(launches, 1)}
+                "algorithmic_flops_per_launch": flops_step / launches_step,
+                "executed_flops_per_step": gemm_flops / args.steps}
 
     # correctness of the benchmarked X: binary64 residual on the GPU
     check = {}
