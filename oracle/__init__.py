@@ -97,6 +97,8 @@ def bind(lib):
     lib.oracle_chol_f64.restype = ci
     lib.oracle_lu_nopiv_f64.argtypes = [i64, dp, i64, dp, i64, ci, ctypes.POINTER(i64)]
     lib.oracle_lu_nopiv_f64.restype = ci
+    lib.oracle_lu_piv_f64.argtypes = [i64, dp, i64, dp, i64, ci, dp, ctypes.POINTER(i64)]
+    lib.oracle_lu_piv_f64.restype = ci
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ci
     return lib
@@ -249,6 +251,40 @@ def lu_nopiv(A, nthreads: int = 0):
     L = np.tril(LU, -1) + np.eye(n)
     U = np.triu(LU)
     return L, U, int(fail.value)
+
+
+def lu_piv(A, nthreads: int = 0):
+    """LU factors with partial pivoting, P A = L U (Gaussian elimination with
+    row exchanges, LAPACK dgetf2's order): returns (L, U, ipiv, fail) with L
+    unit lower triangular, U upper triangular, ipiv[j] (0-based, >= j) the row
+    exchanged with row j at step j, and fail = -1 or the first step whose
+    pivot is zero."""
+    lib = _load()
+    A = _rows(A)
+    n = A.shape[0]
+    if A.shape[1] < n:
+        raise ValueError("A must be n x n")
+    LU = np.empty((n, n), dtype=np.float64)
+    ipiv = np.empty(max(n, 1), dtype=np.int64)
+    fail = ctypes.c_int64(-1)
+    rc = lib.oracle_lu_piv_f64(n, A.ctypes.data, _ld(A), LU.ctypes.data, max(n, 1),
+                               int(nthreads), ipiv.ctypes.data, ctypes.byref(fail))
+    if rc != 0:
+        raise ValueError("oracle_lu_piv_f64 rejected the sizes")
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    return L, U, ipiv[:n].copy(), int(fail.value)
+
+
+def perm_from_ipiv(ipiv) -> np.ndarray:
+    """The row order p with (P A) = A[p] for the exchanges "swap rows j and
+    ipiv[j]", j ascending."""
+    p = np.arange(len(ipiv))
+    for j, q in enumerate(ipiv):
+        q = int(q)
+        if q != j:
+            p[j], p[q] = p[q], p[j]
+    return p
 
 
 def rel_fro_err(X, Xref) -> float:

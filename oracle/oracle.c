@@ -377,6 +377,89 @@ int oracle_lu_nopiv_f64(int64_t n, const double* A, int64_t lda,
   return 0;
 }
 
+/* LU factorization with partial pivoting (row exchanges), P A = L U, L unit
+ * lower triangular with |l_ij| <= 1, U upper triangular: the plain
+ * right-looking elimination of Gaussian elimination with partial pivoting,
+ * the unblocked form of LAPACK's dgetf2.  For j = 0, 1, ..., n - 1:
+ *
+ *   p = the first row i >= j with the largest |a[i][j]|   (ipiv[j] = p)
+ *   exchange rows j and p of the whole working matrix (all n columns)
+ *   if a[j][j] != 0:  l[i][j] = a[i][j] / a[j][j]                 (i > j)
+ *                     a[i][c] = a[i][c] - l[i][j] * a[j][c]      (i, c > j)
+ *
+ * with IEEE binary64, a true division and no contraction.  The abstract and
+ * Sec. I name LU as a factorization built on TRSM; the row exchanges are
+ * what make it apply to every nonsingular matrix.  P A = L U with P the
+ * product of the exchanges: applying "swap rows j and ipiv[j]" for j = 0 ..
+ * n - 1 to A gives L U.
+ *
+ * LU receives L strictly below the diagonal (its unit diagonal is not
+ * stored) and U on and above it (row-major, ld ldu; it may equal A with lda
+ * == ldu); ipiv[j] the row exchanged with row j (0-based, ipiv[j] >= j).
+ * Threads split the rows of each update; every element sees the same
+ * operations in the same order whatever the thread count.  Returns 0, or -1
+ * on bad sizes.  *fail receives -1, or the first j whose pivot is zero (or
+ * not finite); that column is then left unscaled and the elimination goes on
+ * (as LAPACK does with its INFO). */
+int oracle_lu_piv_f64(int64_t n, const double* A, int64_t lda, double* LU, int64_t ldu,
+                      int nthreads, int64_t* ipiv, int64_t* fail) {
+  if (fail != NULL) *fail = -1;
+  if (n < 0) return -1;
+  if (n == 0) return 0;
+  if (lda < n || ldu < n || ipiv == NULL) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    double* ui = LU + i * ldu;
+    const double* ai = A + i * lda;
+    if (ui != ai)
+      for (int64_t j = 0; j < n; ++j) ui[j] = ai[j];
+  }
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#endif
+  for (int64_t j = 0; j < n; ++j) {
+    /* the pivot: first largest magnitude in column j, rows j .. n-1 */
+    int64_t p = j;
+    double best = fabs(LU[j * ldu + j]);
+    for (int64_t i = j + 1; i < n; ++i) {
+      const double v = fabs(LU[i * ldu + j]);
+      if (v > best) {
+        best = v;
+        p = i;
+      }
+    }
+    ipiv[j] = p;
+    if (p != j) {
+      double* rj = LU + j * ldu;
+      double* rp = LU + p * ldu;
+      for (int64_t c = 0; c < n; ++c) {
+        const double t = rj[c];
+        rj[c] = rp[c];
+        rp[c] = t;
+      }
+    }
+    const double piv = LU[j * ldu + j];
+    if (!(piv != 0.0) || !isfinite(piv)) {
+      if (fail != NULL && *fail < 0) *fail = j;
+      continue;
+    }
+    const double* uj = LU + j * ldu;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (n - j > 128)
+#endif
+    for (int64_t i = j + 1; i < n; ++i) {
+      double* ri = LU + i * ldu;
+      const double l = ri[j] / piv;
+      ri[j] = l;
+      for (int64_t c = j + 1; c < n; ++c) {
+        const double term = l * uj[c];
+        ri[c] = ri[c] - term;
+      }
+    }
+  }
+  (void)nthreads;
+  return 0;
+}
+
 /* Number of threads the OpenMP runtime would use by default. */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -16,6 +16,7 @@ import pytest
 import oracle
 from oracle import exact
 from paper_1612_01855_amd import inputs as gen
+from lu_piv_pins import failed_lu_piv_pins
 from norm_pins import failed_norm_pins
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
@@ -52,6 +53,25 @@ NORM_MUTANTS = {
                                 "for (int64_t c = 0; c + 1 < k; ++c) {\n      __float128 v = (__float128)A[i * lda + c];"),
     "lower_sum_not_squared": ("      s += v * v;\n    }\n  /* square root",
                               "      s += v < 0 ? -v : v;\n    }\n  /* square root"),
+}
+
+
+# Planted mistakes in LU with partial pivoting.
+LU_PIV_MUTANTS = {
+    "last_largest_on_ties": ("if (v > best) {\n        best = v;\n        p = i;",
+                             "if (v >= best) {\n        best = v;\n        p = i;"),
+    "signed_not_magnitude": ("const double v = fabs(LU[i * ldu + j]);",
+                             "const double v = LU[i * ldu + j];"),
+    "search_skips_a_row": ("for (int64_t i = j + 1; i < n; ++i) {\n      const double v = fabs",
+                           "for (int64_t i = j + 2; i < n; ++i) {\n      const double v = fabs"),
+    "exchange_skips_L_part": ("for (int64_t c = 0; c < n; ++c) {\n        const double t = rj[c];",
+                              "for (int64_t c = j; c < n; ++c) {\n        const double t = rj[c];"),
+    "no_exchange": ("    if (p != j) {\n      double* rj", "    if (0) {\n      double* rj"),
+    "ipiv_records_step": ("    ipiv[j] = p;", "    ipiv[j] = j;"),
+    "multiplier_multiplies": ("const double l = ri[j] / piv;", "const double l = ri[j] * piv;"),
+    "update_skips_last_column": ("for (int64_t c = j + 1; c < n; ++c) {\n        const double term = l * uj[c];",
+                                 "for (int64_t c = j + 1; c + 1 < n; ++c) {\n        const double term = l * uj[c];"),
+    "update_wrong_sign": ("ri[c] = ri[c] - term;", "ri[c] = ri[c] + term;"),
 }
 
 
@@ -141,3 +161,18 @@ def test_norm_mutant_is_caught(name, tmp_path, monkeypatch):
     monkeypatch.setattr(oracle, "_lib", lib)
     failed = failed_norm_pins(oracle)
     assert failed, f"norm mutant {name} passed every pin"
+
+
+def test_unmodified_source_passes_lu_piv_pins(tmp_path, monkeypatch):
+    monkeypatch.setattr(oracle, "_lib", oracle.bind(_compile(SRC, tmp_path)))
+    assert failed_lu_piv_pins(oracle.lu_piv) == []
+
+
+@pytest.mark.parametrize("name", sorted(LU_PIV_MUTANTS))
+def test_lu_piv_mutant_is_caught(name, tmp_path, monkeypatch):
+    old, new = LU_PIV_MUTANTS[name]
+    assert SRC.count(old) == 1, "mutation anchor not found once in oracle.c"
+    lib = oracle.bind(_compile(SRC.replace(old, new, 1), tmp_path))
+    monkeypatch.setattr(oracle, "_lib", lib)
+    failed = failed_lu_piv_pins(oracle.lu_piv)
+    assert failed, f"LU mutant {name} passed every pin"
