@@ -318,6 +318,55 @@ def lu_bench(args, torch, T, gen, dev, emit):
         torch.cuda.empty_cache()
 
 
+def lu_piv_bench(args, torch, T, gen, dev, emit):
+    """Blocked LU with partial pivoting (binary64) on Gaussian random matrices
+    (no diagonal dominance: exchanges happen at nearly every step): median of
+    3 timed factorizations after a warm one, flops 2 n^3 / 3, backward error
+    ||P A - L U|| / ||P A|| on 64 sampled rows of P A."""
+    sizes = (args.chol_n,) if args.chol_n else (4096, 8192, 16384)
+    blocks = (args.chol_nb,) if args.chol_nb is not None else (0, 256, 512)
+    for n in sizes:
+        g = torch.Generator(device=dev).manual_seed(args.seed + n)
+        A0 = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64)
+        for nb in blocks:
+            f = T.LUPiv(n, nb, device=dev)
+            if nb and f.nb != nb:
+                continue
+            A = torch.empty_like(A0)
+            times = []
+            for it in range(4):
+                A.copy_(A0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                f.factor(A)
+                e1.record()
+                torch.cuda.synchronize()
+                if it:
+                    times.append(e0.elapsed_time(e1))
+            st, idx = f.check()
+            # rows of P A: apply the exchanges to a copy of A0
+            PA = A0.clone()
+            f.apply(PA)
+            gcpu = torch.Generator().manual_seed(args.seed)
+            rows = torch.randint(0, n, (64,), generator=gcpu).to(dev)
+            Ar = A.index_select(0, rows)
+            cols = torch.arange(n, device=dev)
+            Lr = torch.where(cols[None, :] < rows[:, None], Ar, torch.zeros_like(Ar))
+            Lr.scatter_(1, rows[:, None], 1.0)
+            R = PA.index_select(0, rows) - Lr @ torch.triu(A)
+            be = float(torch.linalg.norm(R).item() / torch.linalg.norm(PA.index_select(0, rows)).item())
+            ms = sorted(times)[1]
+            tf = 2.0 * float(n) ** 3 / 3.0 / (ms * 1e-3) / 1e12
+            emit({"suite": "lu_piv", "n": n, "nb": int(f.nb), "auto": nb == 0,
+                  "ms": round(ms, 3), "tflops_2n3_3": round(tf, 2),
+                  "frac_peak": round(tf / PEAK["f64"], 4), "status": T.status_string(st),
+                  "sampled_backward_error": be})
+            log(f"suite lu_piv n={n} nb={f.nb}: {ms:.2f} ms {tf:.2f} TF backward {be:.2e}")
+            del f, A, Ar, Lr, R, PA
+        del A0
+        torch.cuda.empty_cache()
+
+
 def run_suite(args, torch, T, gen, dev):
     """The workload sweeps: n0 sweep and the recursive baseline at n = k = 8192
     (binary64 and binary32), the n/k sweep at n = 16384, and the hard factor in
@@ -420,6 +469,7 @@ def run_suite(args, torch, T, gen, dev):
     # blocked Cholesky and LU (no row exchanges) with inverted-block panel solves
     cholesky_bench(args, torch, T, gen, dev, emit)
     lu_bench(args, torch, T, gen, dev, emit)
+    lu_piv_bench(args, torch, T, gen, dev, emit)
 
     # mixed precision at n = k = 16384 on the ill-conditioned factor (cond ~ 1e6)
     n = k = 16384
@@ -489,18 +539,20 @@ def main():
                     help="instead of the headline step, run only the Cholesky sweep of the suite")
     ap.add_argument("--lu", action="store_true",
                     help="instead of the headline step, run only the LU (no row exchanges) sweep")
+    ap.add_argument("--lu-piv", action="store_true",
+                    help="instead of the headline step, run only the LU with partial pivoting sweep")
     ap.add_argument("--chol-n", type=int, default=0, help="--cholesky / --lu: this n only")
     ap.add_argument("--chol-nb", type=int, default=None,
                     help="--cholesky / --lu: this block size only")
     args = ap.parse_args()
 
-    if args.suite or args.cholesky or args.lu:
+    if args.suite or args.cholesky or args.lu or args.lu_piv:
         import torch
         from paper_1612_01855_amd import inputs as gen
         from paper_1612_01855_amd import trsm as T
         assert torch.cuda.is_available(), "bench.py needs a GPU"
-        if args.cholesky or args.lu:
-            bench_fn = cholesky_bench if args.cholesky else lu_bench
+        if args.cholesky or args.lu or args.lu_piv:
+            bench_fn = cholesky_bench if args.cholesky else lu_bench if args.lu else lu_piv_bench
             bench_fn(args, torch, T, gen, torch.device("cuda:0"),
                      lambda rec: print(json.dumps(rec), flush=True))
         else:

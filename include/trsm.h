@@ -531,6 +531,56 @@ trsm_status trsm_lu_factor(int64_t n, double* A, int64_t lda, int64_t nb, double
 trsm_status trsm_lu_check(const void* workspace, trsm_status* status, int64_t* index);
 
 /*
+ * Blocked LU factorization WITH partial pivoting, P A = L U (binary64; L unit
+ * lower with |l_ij| <= 1, U upper): Gaussian elimination with row exchanges,
+ * the first row with the largest pivot magnitude at each step (LAPACK
+ * dgetrf's exchanges).  Built on the triangular solve of Alg. It-Inv-TRSM
+ * (the abstract and Sec. I name LU as built on TRSM): block columns of nb
+ * (a power of two >= 32) are factored in 32-column panels (one cooperative
+ * launch per panel, one device-wide barrier per column); then each block's
+ * unit lower diagonal block is inverted by Alg. Diagonal-Inverter +
+ * RecTriInv, U(S_j, T_j) = Linv_jj A(S_j, T_j) is one product with the
+ * inverted block, and A(T_j, T_j) -= L(T_j, S_j) U(S_j, T_j).  n <= 65536.
+ *
+ * trsm_lu_piv_sizes(n, nb, &nb_used, &inv_bytes, &workspace_bytes): nb = 0
+ *  picks 256 (n <= 4096) or 512; nb is capped at the next power of two >= n
+ *  (the block size a solve plan gives such an n).  inv_bytes: the Linv
+ *  buffer (m nb x nb blocks); workspace_bytes: device scratch the call
+ *  needs (status words, panel candidates, one block and its inverse, one
+ *  block row of U, split-K partials).  Host only.  TRSM_EINVAL for n <= 0,
+ *  n > 65536, or nb not 0 and not a power of two >= 32.
+ * trsm_lu_piv_factor(n, A, lda, nb, ipiv, Linv, workspace, stream): A
+ *  (device, row-major, lda >= n, 16-byte aligned) is overwritten with L
+ *  strictly below the diagonal (unit diagonal not stored) and U on and above
+ *  it, for the row-exchanged matrix; ipiv (device, n int64) receives the row
+ *  exchanged with row j at step j (0-based, ipiv[j] >= j; apply "swap rows j
+ *  and ipiv[j]" for j ascending to get P A); Linv the inverses of L's
+ *  diagonal blocks (block j at Linv + j nb nb, row-major, ones on the
+ *  diagonal, zeros above; the ragged last block padded with the identity):
+ *  a TRSM_F64 plan with n0 = nb_used solves L Y = B with A as its L and these
+ *  blocks.  workspace (256-byte aligned, caller-owned) of workspace_bytes.
+ *  Asynchronous on `stream` (null: the default stream); allocates nothing.
+ *  TRSM_EINVAL on bad arguments, TRSM_EHIP when a launch fails (including a
+ *  cooperative launch the device cannot make co-resident).
+ * trsm_lu_piv_check(workspace, &status, &index): blocking.  TRSM_OK and -1;
+ *  TRSM_ESINGULAR and the first column whose pivot was zero or not finite
+ *  (the factorization goes on, as LAPACK does, and U is singular); or
+ *  TRSM_EHIP and -1 if a panel's barrier wait gave up (ruled out by the
+ *  cooperative launch; reported rather than hung).
+ * trsm_row_swaps(k0, k1, ipiv, B, ldb, ncols, stream): applies "swap rows k
+ *  and ipiv[k]" for k = k0 .. k1-1 in order to the first ncols columns of the
+ *  device matrix B (row-major, ldb >= ncols): P B for a factorization's
+ *  ipiv.  Asynchronous.
+ */
+trsm_status trsm_lu_piv_sizes(int64_t n, int64_t nb, int64_t* nb_used, size_t* inv_bytes,
+                              size_t* workspace_bytes);
+trsm_status trsm_lu_piv_factor(int64_t n, double* A, int64_t lda, int64_t nb, int64_t* ipiv,
+                               double* Linv, void* workspace, void* stream);
+trsm_status trsm_lu_piv_check(const void* workspace, trsm_status* status, int64_t* index);
+trsm_status trsm_row_swaps(int64_t k0, int64_t k1, const int64_t* ipiv, double* B, int64_t ldb,
+                           int64_t ncols, void* stream);
+
+/*
  * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes
  * every matrix-core product launched by trsm_invert_diag and trsm_solve with
  * this plan record a pair of hipEvents around itself on the call's stream

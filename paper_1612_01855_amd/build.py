@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtrsm.so")
-SOURCES = ["kernels.hip", "trsm.hip", "batch.hip", "serve.hip", "tune.hip", "factor.hip", "crt.hip"]
+SOURCES = ["kernels.hip", "trsm.hip", "batch.hip", "serve.hip", "tune.hip", "factor.hip", "crt.hip", "lupiv.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

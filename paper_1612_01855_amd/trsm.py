@@ -92,7 +92,8 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_serve_poll",
            "trsm_server_stats", "trsm_server_reset_stats", "trsm_server_destroy",
            "trsm_chol_sizes", "trsm_chol_factor", "trsm_chol_check",
-           "trsm_lu_sizes", "trsm_lu_factor", "trsm_lu_check"]
+           "trsm_lu_sizes", "trsm_lu_factor", "trsm_lu_check",
+           "trsm_lu_piv_sizes", "trsm_lu_piv_factor", "trsm_lu_piv_check", "trsm_row_swaps"]
 
 
 class TrsmError(RuntimeError):
@@ -202,6 +203,16 @@ def _load():
     lib.trsm_lu_factor.restype = i32
     lib.trsm_lu_check.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     lib.trsm_lu_check.restype = i32
+    lib.trsm_lu_piv_sizes.argtypes = [i64, i64, ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.trsm_lu_piv_sizes.restype = i32
+    lib.trsm_lu_piv_factor.argtypes = [i64, vp, i64, i64, vp, vp, vp, vp]
+    lib.trsm_lu_piv_factor.restype = i32
+    lib.trsm_lu_piv_check.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.trsm_lu_piv_check.restype = i32
+    lib.trsm_row_swaps.argtypes = [i64, i64, vp, vp, i64, i64, vp]
+    lib.trsm_row_swaps.restype = i32
     return lib
 
 
@@ -445,6 +456,35 @@ def trsm_lu_check(workspace: int):
     return st.value, idx.value
 
 
+def trsm_lu_piv_sizes(n: int, nb: int = 0):
+    """(nb_used, Linv bytes, workspace_bytes) of an LU factorization with
+    partial pivoting."""
+    nbu, lb, wb = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.trsm_lu_piv_sizes(n, nb, ctypes.byref(nbu), ctypes.byref(lb), ctypes.byref(wb)),
+           "trsm_lu_piv_sizes")
+    return nbu.value, lb.value, wb.value
+
+
+def trsm_lu_piv_factor(n: int, A: int, lda: int, nb: int, ipiv: int, Linv: int, workspace: int,
+                       stream: int = 0) -> None:
+    _check(_lib.trsm_lu_piv_factor(n, A, lda, nb, ipiv, Linv, workspace, stream),
+           "trsm_lu_piv_factor")
+
+
+def trsm_lu_piv_check(workspace: int):
+    """(status, index) of the last pivoted LU factorization on `workspace`
+    (blocking)."""
+    st, idx = ctypes.c_int(), ctypes.c_int64()
+    _check(_lib.trsm_lu_piv_check(workspace, ctypes.byref(st), ctypes.byref(idx)),
+           "trsm_lu_piv_check")
+    return st.value, idx.value
+
+
+def trsm_row_swaps(k0: int, k1: int, ipiv: int, B: int, ldb: int, ncols: int,
+                   stream: int = 0) -> None:
+    _check(_lib.trsm_row_swaps(k0, k1, ipiv, B, ldb, ncols, stream), "trsm_row_swaps")
+
+
 # ---- torch-tensor convenience (memory ownership only) ------------------------
 
 def _stream_handle(torch, device) -> int:
@@ -661,6 +701,102 @@ def lu_nopiv(A, nb: int = 0):
     L = torch.tril(F, -1)
     L.diagonal().fill_(1.0)
     return L, torch.triu(F)
+
+
+class LUPiv:
+    """Owns the ipiv, Linv and workspace buffers of an LU factorization with
+    partial pivoting of one size (torch tensors, 256-byte aligned views)."""
+
+    def __init__(self, n: int, nb: int = 0, device: str = "cuda"):
+        import torch
+        self.n = n
+        self.nb, lb, wb = trsm_lu_piv_sizes(n, nb)
+        self.ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=device)
+        self._linv = torch.empty(max(lb, 1) + 256, dtype=torch.uint8, device=device)
+        self._ws = torch.empty(max(wb, 1) + 256, dtype=torch.uint8, device=device)
+
+    @staticmethod
+    def _aligned(buf) -> int:
+        return (buf.data_ptr() + 255) // 256 * 256
+
+    @property
+    def linv_ptr(self) -> int:
+        return self._aligned(self._linv)
+
+    @property
+    def workspace_ptr(self) -> int:
+        return self._aligned(self._ws)
+
+    def factor(self, A) -> None:
+        """In place: A becomes L (strictly lower, unit diagonal implied) and U
+        of P A = L U; self.ipiv the exchanges."""
+        import torch
+        if A.shape[0] != self.n or A.shape[1] < self.n:
+            raise ValueError("A must be an n x n float64 tensor")
+        trsm_lu_piv_factor(self.n, _dev(A, torch.float64, "A"), _ld(A), self.nb,
+                           self.ipiv.data_ptr(), self.linv_ptr, self.workspace_ptr,
+                           _stream_handle(torch, A.device))
+
+    def apply(self, B) -> None:
+        """B <- P B, in place (B float64, n rows)."""
+        import torch
+        trsm_row_swaps(0, self.n, self.ipiv.data_ptr(), _dev(B, torch.float64, "B"), _ld(B),
+                       B.shape[1], _stream_handle(torch, B.device))
+
+    def linv_blocks(self):
+        import torch
+        m = (self.n + self.nb - 1) // self.nb
+        off = self.linv_ptr - self._linv.data_ptr()
+        return self._linv[off:off + m * self.nb * self.nb * 8].view(torch.float64).view(
+            m, self.nb, self.nb)
+
+    def check(self):
+        return trsm_lu_piv_check(self.workspace_ptr)
+
+
+def lu_piv(A, nb: int = 0):
+    """(L, U, ipiv) with P A = L U by partial pivoting, on the GPU (A
+    float64).  Raises TrsmError(ESINGULAR) at a zero pivot."""
+    import torch
+    n = A.shape[0]
+    F = A.clone()
+    f = LUPiv(n, nb, device=A.device)
+    f.factor(F)
+    st, idx = f.check()
+    if st != OK:
+        raise TrsmError(st, f"lu_piv (column {idx})")
+    L = torch.tril(F, -1)
+    L.diagonal().fill_(1.0)
+    return L, torch.triu(F), f.ipiv.clone()
+
+
+def lu_piv_solve(A, B, nb: int = 0):
+    """X = A^{-1} B on the GPU (binary64) by LU with partial pivoting: P B,
+    then L Y = P B with the factorization's inverted blocks, then U X = Y with
+    an upper plan reading U in the factored copy of A."""
+    import torch
+    n, k = B.shape
+    F = A.clone()
+    f = LUPiv(n, nb, device=A.device)
+    f.factor(F)
+    PB = B.clone().contiguous()
+    f.apply(PB)
+    fwd = Solver.create(n, k, "f64", n0=f.nb, device=B.device)
+    up = Solver.create(n, k, "f64", 0, FLAG_UPPER, device=B.device)
+    try:
+        if fwd.info.n0 != f.nb:
+            raise ValueError(f"lu_piv_solve: blocks of {f.nb} rows do not fit a plan for n = {n}")
+        Y = fwd.solve(F, PB, linv_ptr=f.linv_ptr)
+        up.invert(F)
+        X = up.solve(F, Y)
+        st, idx = f.check()
+        if st != OK:
+            raise TrsmError(st, f"lu_piv_solve (column {idx})")
+        return X
+    finally:
+        torch.cuda.current_stream(B.device).synchronize()
+        fwd.close()
+        up.close()
 
 
 def lu_solve(A, B, nb: int = 0):

@@ -343,3 +343,25 @@ def test_binding_refuses_host_tensors_and_overlapping_rows(T):
         T._ld(torch.zeros(64, dtype=torch.float64).as_strided((8, 8), (1, 1)))
     assert T._ld(torch.zeros((5, 0))) == 1
     assert T._ld(torch.zeros((3, 7))[:, :4]) == 7
+
+
+def test_pivoted_lu_sizes_and_validation_without_gpu(T):
+    nbu, lb, wb = T.trsm_lu_piv_sizes(1000)
+    assert nbu == 256 and lb == 4 * 256 * 256 * 8 and wb > 0
+    assert T.trsm_lu_piv_sizes(20000)[0] == 512
+    assert T.trsm_lu_piv_sizes(20)[0] == 32          # capped at pow2(n), at least one panel
+    assert T.trsm_lu_piv_sizes(100, 512)[0] == 128
+    lib = T._lib
+    a, b, c = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+    for n, nb in [(0, 0), (-5, 0), (65537, 0), (100, 48), (100, 16), (100, -64)]:
+        assert lib.trsm_lu_piv_sizes(n, nb, ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.byref(c)) == T.EINVAL
+    # null or misaligned pointers are refused before any device work
+    assert lib.trsm_lu_piv_factor(100, None, 100, 0, None, None, None, None) == T.EINVAL
+    assert lib.trsm_lu_piv_factor(100, 256, 99, 0, 256, 256, 256, None) == T.EINVAL   # lda < n
+    assert lib.trsm_lu_piv_factor(100, 256, 100, 0, 256, 256, 300, None) == T.EINVAL  # ws align
+    st = ctypes.c_int()
+    assert lib.trsm_lu_piv_check(None, ctypes.byref(st), None) == T.EINVAL
+    assert lib.trsm_row_swaps(0, 5, None, None, 4, 4, None) == T.EINVAL
+    assert lib.trsm_row_swaps(3, 2, None, None, 4, 4, None) == T.EINVAL
+    assert lib.trsm_row_swaps(0, 0, None, None, 4, 4, None) == T.OK             # nothing to do
