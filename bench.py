@@ -28,6 +28,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+MIXED_TOL = 1e-12   # relative error target of the mixed-precision comparison
 METRIC = ("TRSM TFLOP/s (n²k) at n=k=16384; served p50/p99 latency; "
           "mixed vs plain FP64")
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # TFLOP/s, dense
@@ -695,35 +696,49 @@ def main():
 
     mixed = {}
     if not args.no_mixed and args.precision == "f64":
-        for prec in ("bf16", "f16", "fp8"):
-            try:
-                s2 = T.Solver.create(n, k, prec, args.n0, 0, device=dev)
-                Xm = torch.empty_like(Bd)
-                s2.invert(Ld)
-                inf = T.Info()
-                s2.solve(Ld, Bd, Xm, info=inf)         # warm
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                reps = 2
-                for _ in range(reps):
+        # refinement to the 1e-12 relative error the comparison asks for, then
+        # to binary64's backward-error level (tolerance 0)
+        mixed = {"tolerance": MIXED_TOL, "binary64_level": {}}
+        for tol in (MIXED_TOL, 0.0):
+            dest = mixed if tol > 0 else mixed["binary64_level"]
+            for prec in ("bf16", "f16", "fp8"):
+                try:
+                    s2 = T.Solver.create(n, k, prec, args.n0, 0, device=dev, tolerance=tol)
+                    Xm = torch.empty_like(Bd)
                     s2.invert(Ld)
-                    s2.solve(Ld, Bd, Xm, info=inf)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - t0) * 1e3 / reps
-                diff = float(torch.linalg.norm(Xm - Xd).item() / torch.linalg.norm(Xd).item())
-                mixed[prec] = {"ms_per_solve": round(ms, 3),
-                               "tflops_n2k": round(flops_step / (ms * 1e-3) / 1e12, 3),
-                               "speedup_vs_f64": round(ms_step / ms, 3),
-                               "corrections": inf.iterations, "converged": bool(inf.converged),
-                               "backward_error": inf.backward_error,
-                               "unrefined_error_est": inf.unrefined_error,
-                               "rel_diff_vs_f64_solve": diff}
-                log(f"mixed {prec}: {ms:.2f} ms/solve, {inf.iterations} corrections, diff {diff:.1e}")
-                del Xm
-                s2.close()
-                torch.cuda.empty_cache()
-            except Exception as e:  # report, never hide
-                mixed[prec] = {"error": str(e)}
+                    inf = T.Info()
+                    s2.solve(Ld, Bd, Xm, info=inf)         # warm
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    reps = 2
+                    for _ in range(reps):
+                        s2.invert(Ld)
+                        s2.solve(Ld, Bd, Xm, info=inf)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3 / reps
+                    diff = float(torch.linalg.norm(Xm - Xd).item() / torch.linalg.norm(Xd).item())
+                    dest[prec] = {"ms_per_solve": round(ms, 3),
+                                  "tflops_n2k": round(flops_step / (ms * 1e-3) / 1e12, 3),
+                                  "speedup_vs_f64": round(ms_step / ms, 3),
+                                  "corrections": inf.iterations, "converged": bool(inf.converged),
+                                  "status": T.status_string(s2.last_status),
+                                  # of the last residual computed (with a tolerance the
+                                  # final correction is added after it)
+                                  "backward_error_last_residual": inf.backward_error,
+                                  "unrefined_error_est": inf.unrefined_error,
+                                  "rel_diff_vs_f64_solve": diff}
+                    if tol > 0:
+                        dest[prec]["within_tolerance"] = bool(diff <= tol)
+                    log(f"mixed {prec} (tolerance {tol:g}): {ms:.2f} ms/solve, "
+                        f"{inf.iterations} corrections, diff {diff:.1e}")
+                    del Xm
+                    s2.close()
+                    torch.cuda.empty_cache()
+                except Exception as e:  # report, never hide
+                    dest[prec] = {"error": str(e)}
+        ok = [v["speedup_vs_f64"] for pr, v in mixed.items()
+              if pr in ("bf16", "f16", "fp8") and "error" not in v and v["within_tolerance"]]
+        mixed["best_speedup_vs_f64_within_tolerance"] = max(ok) if ok else None
 
     serving = None
     if not args.no_serving and args.precision == "f64":

@@ -207,11 +207,22 @@ trsm_status trsm_plan_last_error(trsm_plan_t plan, trsm_status* status, int64_t*
  *  X may be the same buffer as B when ldx == ldb (solve in place); any
  *  other overlap is TRSM_EINVAL.
  *  F64/F32 plans: asynchronous; `info` (nullable) receives iterations = 0.
- *  Mixed plans: iterative refinement (low-precision sweep, binary64
- *  residual B - L X, correction) until ||D||_F/||X||_F <= 1e-13 or the
- *  backward error is <= 4u; this reads two norms back to the host per
- *  iteration, so the call returns after the solve has finished.  Returns
- *  TRSM_ENOTCONVERGED after 10 corrections.
+ *  Mixed plans: iterative refinement X = D_0 + D_1 + ..., each D_j the
+ *  low-precision sweep of the residual B - L (D_0 + ... + D_{j-1}), the
+ *  residual computed exactly (integer products on the int8 matrix cores in
+ *  a residue number system, one binary64 rounding per element) for L with
+ *  its strictly lower part rounded to the bits binary64's backward-error
+ *  level needs.  Stopping test (default, tolerance 0): the backward error
+ *  ||B - L X||_F / (||L||_F ||X||_F) <= 4u, or a correction
+ *  ||D_j||_F <= 1e-15 ||X||_F, or the observed contraction
+ *  rho = ||D_j|| / ||D_{j-1}|| <= 1/2 predicting ||D_j|| rho <= 1e-14 ||X||.
+ *  With trsm_plan_set_tolerance(plan, tol > 0) also: ||D_j|| rho <= tol
+ *  ||X|| with D_0 the first sweep's result (||D_0|| = ||X||).  The call reads
+ *  norms back to the host after every residual and correction, so it
+ *  returns after the solve has finished.  Returns TRSM_ENOTCONVERGED after
+ *  10 corrections (X holds the last iterate); `info` (nullable) receives
+ *  the corrections, the last backward error and correction, and the first
+ *  correction as unrefined_error.
  *  With TRSM_FLAG_RECURSIVE the plan solves by the recursive baseline
  *  (Alg. Rec-TRSM order: X1 = solve(L11, B1); B2 -= L21 X1; X2 = solve(L22,
  *  B2), substitution at the leaves, no inversion) and Linv may be NULL.
@@ -579,6 +590,22 @@ trsm_status trsm_lu_piv_factor(int64_t n, double* A, int64_t lda, int64_t nb, in
 trsm_status trsm_lu_piv_check(const void* workspace, trsm_status* status, int64_t* index);
 trsm_status trsm_row_swaps(int64_t k0, int64_t k1, const int64_t* ipiv, double* B, int64_t ldb,
                            int64_t ncols, void* stream);
+
+/*
+ * trsm_plan_set_tolerance -- accuracy target of a mixed-precision plan's
+ * refinement (the paper solves in one precision; refinement is this
+ * library's addition around the sweep of Alg. It-Inv-TRSM).  tol = 0 (the
+ * default) refines to binary64's backward-error level; 0 < tol < 1 also
+ * stops once the relative forward error left, estimated from the last
+ * correction and the observed contraction, is <= tol, and makes the first
+ * sweep a full-accuracy one (binary32 diagonal apply) so that a half-
+ * precision sweep reaches tol = 1e-12 on a well-conditioned L with one
+ * exact residual.  The estimate assumes each sweep contracts the error by
+ * a similar factor; it is not a bound.  Binary64 and binary32 plans keep
+ * the value and ignore it.  Host only; TRSM_EINVAL for a null plan or tol
+ * outside [0, 1) (NaN included).
+ */
+trsm_status trsm_plan_set_tolerance(trsm_plan_t plan, double tol);
 
 /*
  * Launch timing for roofline reports.  trsm_plan_set_timing(plan, 1) makes

@@ -193,6 +193,9 @@ struct trsm_plan_s {
   int64_t n = 0, k = 0, n0 = 1, m = 0, leaf = 1, n0_paper = 1;
   trsm_precision prec = TRSM_F64;
   uint32_t flags = 0;
+  // mixed plans: target of the estimated relative forward error of the
+  // refined X (0: refine to binary64's backward-error level)
+  double tol = 0.0;
   // Linv buffer layout (byte offsets)
   size_t off_linv64 = 0, off_linv32 = 0, off_llow = 0, off_rscale = 0, off_lnorm = 0, off_lpart = 0;
   // transposed plans: U = L^T (n x ldu, upper) and the blocks Uinv_ii = Linv_ii^T
@@ -721,6 +724,15 @@ int crt_moduli(int a, int bmin, int64_t n, int* b_out) {
 // correction predicted from the observed contraction,
 // ||D_j|| * (||D_j|| / ||D_{j-1}||), falls below 1e-14 ||X||, or when a
 // correction falls below 1e-15 ||X||; at most 10 corrections.
+//
+// With a tolerance tol > 0 (trsm_plan_set_tolerance) the target is a relative
+// forward error of tol instead of binary64's level: the first piece is the
+// full-accuracy sweep (binary32 diagonal apply) rounded to the wide width, so
+// that it counts as correction 0 with ||D_0|| = ||X||, and the refinement
+// also stops once the error left after adding D_j, predicted as
+// ||D_j|| * rho with rho = ||D_j|| / ||D_{j-1}|| <= 1/2, is <= tol ||X||.  A
+// 16-bit sweep whose own error is below sqrt(tol) then needs one exact
+// residual and one correction.
 template <typename TL>
 trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, const char* lbuf,
                         const double* B, int64_t ldb, double* X, int64_t ldx, char* ws,
@@ -758,7 +770,9 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   double scale = pow2_scale_for(h[1]);
   // the first sweep's result is rounded to about 8 bits before the first
   // residual, so its diagonal apply may run in 16 bits as well
-  const bool coarse = !(P.flags & TRSM_FLAG_NO_REFINE) && !std::is_same<TL, fp8_t>::value;
+  const double tol = P.tol;
+  const bool coarse = !(P.flags & TRSM_FLAG_NO_REFINE) && !std::is_same<TL, fp8_t>::value &&
+                      tol == 0.0;
   TRSM_TRY(low_sweep<TL>(P, Linv32, Llow, rscale, B, ldb, scale, Rl, D, XlowT, amax, xinv, s,
                          coarse ? (const TL*)(lbuf + P.off_linv16) : nullptr,
                          (const float*)(lbuf + P.off_linv16_rs)));
@@ -777,7 +791,7 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
   if (alias) return TRSM_EINVAL;  // refinement needs the original B (checked earlier too)
 
   int b0 = 0, b1 = 0;
-  const int P0 = crt_moduli(a, 7, n, &b0);
+  const int P0 = crt_moduli(a, tol > 0.0 ? 20 : 7, n, &b0);
   const int P1 = crt_moduli(a, 20, n, &b1);
   if (P0 < 0 || P1 < 0) return TRSM_EINVAL;
 
@@ -804,9 +818,12 @@ trsm_status solve_mixed(const trsm_plan_s& P, const double* L, int64_t ldl, cons
         if (j == 1) info->unrefined_error = corr;
       }
       bool done = corr <= 1e-15;
-      if (!done && prev > 0) {
-        const double rho = corr / prev;
-        done = rho <= 0.5 && corr * rho <= 1e-14;
+      // the previous correction; without a coarse first piece the first
+      // sweep's result is correction 0, of relative size 1
+      const double before = prev > 0 ? prev : (tol > 0.0 ? 1.0 : -1.0);
+      if (!done && before > 0) {
+        const double rho = corr / before;
+        done = rho <= 0.5 && corr * rho <= std::max(tol, 1e-14);
       }
       prev = corr;
       if (done || j == 10) {
@@ -1339,6 +1356,12 @@ trsm_status trsm_residual(int64_t n, int64_t k, const double* L, int64_t ldl, co
   norms[0] = sqrt(h[0]);
   norms[1] = sqrt(h[2]);
   norms[2] = h[1];
+  return TRSM_OK;
+}
+
+trsm_status trsm_plan_set_tolerance(trsm_plan_t P, double tol) {
+  if (!P || !(tol >= 0.0) || !(tol < 1.0)) return TRSM_EINVAL;
+  P->tol = tol;
   return TRSM_OK;
 }
 

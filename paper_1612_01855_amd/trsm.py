@@ -84,7 +84,8 @@ REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_UNKNOWN = range(5)
 EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_get_info",
            "trsm_plan_destroy", "trsm_invert_diag", "trsm_plan_last_error", "trsm_solve",
            "trsm_solve_noalloc", "trsm_solve_noalloc_max_bytes",
-           "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_timing",
+           "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_tolerance",
+           "trsm_plan_set_timing",
            "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
            "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
@@ -142,6 +143,8 @@ def _load():
     lib.trsm_residual.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
                                   ctypes.POINTER(ctypes.c_double), vp]
     lib.trsm_residual.restype = i32
+    lib.trsm_plan_set_tolerance.argtypes = [vp, ctypes.c_double]
+    lib.trsm_plan_set_tolerance.restype = i32
     lib.trsm_plan_set_timing.argtypes = [vp, i32]
     lib.trsm_plan_set_timing.restype = i32
     lib.trsm_plan_timing.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -288,6 +291,10 @@ def trsm_residual(n: int, k: int, L: int, ldl: int, X: int, ldx: int, B: int, ld
     _check(_lib.trsm_residual(n, k, L, ldl, X, ldx, B, ldb, R, ldr, workspace, norms, stream),
            "trsm_residual")
     return tuple(norms)
+
+
+def trsm_plan_set_tolerance(plan: int, tol: float) -> None:
+    _check(_lib.trsm_plan_set_tolerance(plan, float(tol)), "trsm_plan_set_tolerance")
 
 
 def trsm_plan_set_timing(plan: int, enable: bool = True) -> None:
@@ -519,9 +526,14 @@ class Solver:
 
     @classmethod
     def create(cls, n: int, k: int, precision: str = "f64", n0: int = 0, flags: int = 0,
-               device: str = "cuda"):
+               device: str = "cuda", tolerance: float = 0.0):
         import torch
         plan = trsm_plan(n, k, PRECISIONS[precision], n0, flags)
+        try:
+            trsm_plan_set_tolerance(plan, tolerance)
+        except Exception:
+            trsm_plan_destroy(plan)
+            raise
         info = trsm_plan_get_info(plan)
         linv = torch.empty(max(info.linv_bytes, 1) + 256, dtype=torch.uint8, device=device)
         ws = torch.empty(max(info.workspace_bytes, 1) + 256, dtype=torch.uint8, device=device)
@@ -833,10 +845,12 @@ def lu_solve(A, B, nb: int = 0):
         up.close()
 
 
-def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None):
-    """X = L^{-1} B on the GPU: plan, invert the diagonal blocks, sweep."""
+def solve(L, B, precision: str = "f64", n0: int = 0, flags: int = 0, info: Optional[Info] = None,
+          tolerance: float = 0.0):
+    """X = L^{-1} B on the GPU: plan, invert the diagonal blocks, sweep
+    (mixed precisions: refined to `tolerance`, 0 = binary64's level)."""
     n, k = B.shape
-    s = Solver.create(n, k, precision, n0, flags, device=B.device)
+    s = Solver.create(n, k, precision, n0, flags, device=B.device, tolerance=tolerance)
     try:
         if not (flags & FLAG_RECURSIVE):
             s.invert(L)

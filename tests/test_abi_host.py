@@ -116,6 +116,25 @@ def test_mixed_plan_has_low_precision_copies(T):
         T.trsm_plan_destroy(pb)
 
 
+def test_plan_tolerance_validation(T):
+    lib = T._lib
+    assert lib.trsm_plan_set_tolerance(None, 1e-12) == T.EINVAL
+    p = T.trsm_plan(512, 64, T.MIXED_F16, 128, 0)
+    try:
+        for bad in (-1e-12, 1.0, 2.0, float("nan"), float("inf")):
+            assert lib.trsm_plan_set_tolerance(p, bad) == T.EINVAL
+        for good in (0.0, 1e-12, 0.5):
+            assert lib.trsm_plan_set_tolerance(p, good) == T.OK
+    finally:
+        T.trsm_plan_destroy(p)
+    # binary64 plans keep the value and ignore it
+    p = T.trsm_plan(64, 8, T.F64, 16, 0)
+    try:
+        assert lib.trsm_plan_set_tolerance(p, 1e-12) == T.OK
+    finally:
+        T.trsm_plan_destroy(p)
+
+
 def test_solve_argument_validation_without_gpu(T):
     p = T.trsm_plan(64, 8, T.F64, 16, 0)
     try:

@@ -45,12 +45,12 @@ def sample_cols(k, seed):
 
 
 def gpu_solve_cols(torch, T, Ld, Bd, precision, n0=0, flags=0, info=None, cols=None,
-                   status=None):
+                   status=None, tolerance=0.0):
     """Plan, invert, solve on the GPU (as the benchmark does); return the
     requested columns of X as float64 on the host, and the full X tensor
     (the solve's status is appended to `status` when given)."""
     n, k = Bd.shape
-    s = T.Solver.create(n, k, precision, n0, flags, device=Bd.device)
+    s = T.Solver.create(n, k, precision, n0, flags, device=Bd.device, tolerance=tolerance)
     try:
         if not (flags & T.FLAG_RECURSIVE):
             s.invert(Ld)
@@ -127,6 +127,29 @@ def test_mixed_refined_n16384_k16384(torch, T, prec):
         f"unrefined {info.unrefined_error:.1e}, sampled rel err {err:.2e}")
     assert info.converged == 1
     assert err <= TOL64
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
+def test_mixed_to_tolerance_n16384_k16384(torch, T, prec):
+    """The benchmark's mixed configuration: refinement to 1e-12 on the full
+    n = k = 16384 system, sampled columns against the oracle; the half-
+    precision sweep needs one exact residual and one correction there."""
+    n = k = 16384
+    L, B = gen.easy_system(n, k, 2, upper=np.nan)
+    cols = sample_cols(k, 103)
+    info = T.Info()
+    status = []
+    Xs, X = gpu_solve_cols(torch, T, torch.from_numpy(L).cuda(), torch.from_numpy(B).cuda(),
+                           prec, info=info, cols=cols, status=status, tolerance=1e-12)
+    del X
+    torch.cuda.empty_cache()
+    err = oracle.rel_fro_err(Xs, oracle_cols(L, B, cols))
+    log(f"full size {prec} tol 1e-12: {info.iterations} corrections, "
+        f"first correction {info.unrefined_error:.1e}, sampled rel err {err:.2e}")
+    assert info.converged == 1 and status[0] == T.OK
+    assert err <= 1e-12
+    if prec == "f16":
+        assert info.iterations == 1
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -321,6 +321,52 @@ def test_mixed_hard_matrix(torch, T, prec):
             (info.converged == 0 and status == T.ENOTCONVERGED)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("n,k,n0", [(512, 64, 128), (1000, 40, 0), (2100, 96, 256)])
+def test_mixed_to_tolerance(torch, T, prec, n, k, n0):
+    """Refinement to a relative error of 1e-12 (trsm_plan_set_tolerance):
+    the result is within 1e-12 of the oracle, and a half-precision sweep
+    gets there with at most two corrections (one exact residual when its own
+    error is below 1e-6)."""
+    L, B = gen.easy_system(n, k, 53, upper=np.nan)
+    info = T.Info()
+    Ld, Bd = dev(torch, L), dev(torch, B)
+    X = host(T.solve(Ld, Bd, precision=prec, n0=n0, info=info, tolerance=1e-12))
+    err = oracle.rel_fro_err(X, oracle.trsm(L, B))
+    log(f"{prec} n={n} k={k} tol 1e-12: rel err {err:.2e} after {info.iterations} corrections "
+        f"(first correction {info.unrefined_error:.1e})")
+    assert info.converged == 1
+    assert err <= 1e-12
+    if prec == "f16":
+        assert info.iterations <= 2
+        if info.unrefined_error <= 1e-6:
+            assert info.iterations == 1
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_mixed_to_tolerance_hard_matrix(torch, T, prec):
+    # cond(L) ~ 1e6: more corrections; the backward error of the result is
+    # bounded by its forward error, so it must reach the tolerance too
+    n, k = 512, 8
+    L = gen.hard_lower(n, 3)
+    B = gen.rhs(n, k, 3)
+    info = T.Info()
+    s = T.Solver.create(n, k, prec, tolerance=1e-12)
+    try:
+        Ld, Bd = dev(torch, L), dev(torch, B)
+        s.invert(Ld)
+        X = host(s.solve(Ld, Bd, info=info))
+        status = s.last_status
+    finally:
+        s.close()
+    berr = oracle.backward_err(L, X, B)
+    log(f"mixed {prec} hard L tol 1e-12: {info.iterations} corrections, "
+        f"converged={info.converged}, backward {berr:.2e}, forward vs binary128 "
+        f"{oracle.rel_fro_err(X, oracle.trsm_q(L, B)):.2e}")
+    assert info.converged == 1 and status == T.OK
+    assert berr <= 1e-12
+
+
 # ---- residual entry point -----------------------------------------------------
 
 def test_residual_entry_point(torch, T):
