@@ -88,6 +88,21 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
     nf = args.serve_factors
     sizes = gen.serving_factor_sizes(nf, args.seed + 11)
     n0 = args.serve_n0
+    tune = None
+    if n0 == 0:
+        # the block size from the batch autotuner: one system per factor, k
+        # drawn from the requests' width distribution, binary32 sweeps (the
+        # server's); timed as graph replays of the batched sweep
+        ks = gen.log_uniform_int(gen.rng(args.seed + 13), 1, 512, size=nf)
+        t0 = time.perf_counter()
+        r = T.trsm_batch_autotune([int(v) for v in sizes], [int(v) for v in ks], T.F32, 3)
+        n0 = int(r.n0)
+        tune = {"n0": n0, "ms": round(r.ms, 3), "full_inversion_n0": int(r.default_n0),
+                "full_inversion_ms": round(r.default_ms, 3), "candidates": int(r.candidates),
+                "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"serving: batch autotune n0={n0} ({r.ms:.2f} ms per batched sweep; full inversion "
+            f"{r.default_ms:.2f} ms), {r.candidates} candidates in {tune['seconds']} s")
+        torch.cuda.empty_cache()
     resident = 0
     for n in sizes:
         n0f = min(n0, 512 if chol else n0, 1 << (int(n) - 1).bit_length())
@@ -193,6 +208,7 @@ def serving_bench(args, torch, T, gen, dev, chol=False):
         out = {"factors": nf, "n_range": [int(sizes.min()), int(sizes.max())],
                "k_range": [1, 512], "saturation_rps": round(sat_rps, 1),
                "hbm_budget_gib": round(budget / 2**30, 2), "n0_max": n0,
+               "n0_source": "batch autotune" if tune else "fixed", "batch_autotune": tune,
                "precision": "binary64 in/out; binary32 sweeps, binary64 residuals, refined per "
                             "request to ||B-LX||_F <= sqrt(n) 2^-53 ||L||_F ||X||_F",
                "problem": "A X = B, A = L L^T (flops 2 n^2 k)" if chol else "L X = B"}
@@ -526,8 +542,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-factors", type=int, default=256)
-    ap.add_argument("--serve-n0", type=int, default=4096,
-                    help="server block size (>= n: each factor fully inverted at registration; 64: persistent sweeps)")
+    ap.add_argument("--serve-n0", type=int, default=0,
+                    help="server block size (0: the batch autotuner's choice for the mix; >= n: each "
+                         "factor fully inverted at registration; 64: persistent sweeps)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured saturation rate")

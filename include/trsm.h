@@ -336,6 +336,38 @@ trsm_status trsm_batch_check(trsm_batch_t batch, const void* workspace);
 trsm_status trsm_batch_destroy(trsm_batch_t batch);
 
 /*
+ * trsm_batch_autotune -- the common block size of a batch, measured (the
+ * batched counterpart of trsm_autotune; Sec. VIII leaves n0 to experiment).
+ * Builds `count` synthetic systems of sizes n[i] x n[i] and n[i] x k[i] in
+ * precision prec (TRSM_F64 or TRSM_F32) on the current device, and for each
+ * candidate n0 -- the full inversion min(next power of two >= max n, 4096)
+ * first (the incumbent), then 64 (the persistent form), 128, ... below it --
+ * inverts every system's diagonal blocks, makes the batch and times `reps`
+ * replays of its captured graph (trsm_batch_run with use_graph, on a stream
+ * of its own; the inversions are not timed: factors are inverted once and
+ * kept).  The median-fastest n0 wins if it is at least 1 % faster than the
+ * incumbent; it is recorded in a process-wide table keyed by (precision,
+ * ceil(log2 count), ceil(log2 max n), ceil(log2 max k)), which
+ * trsm_batch_autotune_lookup reads (*n0 = 0 without a record).  Blocking;
+ * allocates and frees its own device buffers (sum of 8 (n^2 + 2 n k) bytes
+ * for binary64; more than 64 GiB is TRSM_ENOMEM).  TRSM_EINVAL for count <= 0,
+ * null arrays, an n[i] or k[i] outside [1, 65536], reps <= 0 or a null
+ * `out`.  trsm_autotune_clear forgets these records too.  Thread-safe.
+ */
+typedef struct trsm_batch_tune_result {
+  int64_t n0;          /* fastest common block size (64: the persistent form) */
+  double ms;           /* its median trsm_batch_run time (graph replay) */
+  int64_t default_n0;  /* the full inversion's block size ... */
+  double default_ms;   /* ... and its median time */
+  int32_t candidates;  /* block sizes timed */
+} trsm_batch_tune_result;
+
+trsm_status trsm_batch_autotune(int32_t count, const int64_t* n, const int64_t* k,
+                                trsm_precision prec, int32_t reps, trsm_batch_tune_result* out);
+trsm_status trsm_batch_autotune_lookup(int32_t count, const int64_t* n, const int64_t* k,
+                                       trsm_precision prec, int64_t* n0);
+
+/*
  * Serving -- continuous batching of solves against resident factors.
  *
  * Each request is solved by iterative refinement around the sweep of Alg.

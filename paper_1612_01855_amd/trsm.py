@@ -55,6 +55,11 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_int32)]
 
 
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("ms", ctypes.c_double), ("default_n0", ctypes.c_int64),
+                ("default_ms", ctypes.c_double), ("candidates", ctypes.c_int32)]
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int64), ("L", ctypes.c_void_p),
                 ("ldl", ctypes.c_int64), ("Linv", ctypes.c_void_p), ("B", ctypes.c_void_p),
@@ -87,6 +92,7 @@ EXPORTS = ["trsm_status_string", "trsm_last_hip_error", "trsm_plan", "trsm_plan_
            "trsm_residual_workspace_bytes", "trsm_residual", "trsm_plan_set_tolerance",
            "trsm_plan_set_timing",
            "trsm_plan_timing", "trsm_autotune", "trsm_autotune_lookup", "trsm_autotune_clear",
+           "trsm_batch_autotune", "trsm_batch_autotune_lookup",
            "trsm_batch_create", "trsm_batch_workspace_bytes",
            "trsm_batch_run", "trsm_batch_check", "trsm_batch_destroy", "trsm_server_create",
            "trsm_server_create_ex", "trsm_server_register_L", "trsm_server_register_chol", "trsm_serve_submit", "trsm_serve_request_bytes",
@@ -154,6 +160,12 @@ def _load():
     lib.trsm_autotune.restype = i32
     lib.trsm_autotune_lookup.argtypes = [i64, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(u32)]
     lib.trsm_autotune_lookup.restype = i32
+    lib.trsm_batch_autotune.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(i64), i32,
+                                        ctypes.c_int32, ctypes.POINTER(BatchTuneResult)]
+    lib.trsm_batch_autotune.restype = i32
+    lib.trsm_batch_autotune_lookup.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(i64), i32,
+                                               ctypes.POINTER(i64)]
+    lib.trsm_batch_autotune_lookup.restype = i32
     lib.trsm_autotune_clear.argtypes = []
     lib.trsm_autotune_clear.restype = i32
     lib.trsm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(BatchItem), i32, i64,
@@ -331,6 +343,36 @@ def trsm_autotune(n: int, k: int, precision: int, reps: int = 3, stream: int = 0
     r = TuneResult()
     _check(_lib.trsm_autotune(n, k, precision, reps, stream, ctypes.byref(r)), "trsm_autotune")
     return r
+
+
+def _i64_array(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int64 * max(len(vals), 1))(*vals), len(vals)
+
+
+def trsm_batch_autotune(ns, ks, precision: int, reps: int = 3) -> BatchTuneResult:
+    """Common block size of a batch of systems of sizes (ns[i], ks[i]),
+    measured on the device (blocking)."""
+    if len(ns) != len(ks):
+        raise ValueError("ns and ks must have the same length")
+    an, c = _i64_array(ns)
+    ak, _ = _i64_array(ks)
+    r = BatchTuneResult()
+    _check(_lib.trsm_batch_autotune(c, an, ak, precision, reps, ctypes.byref(r)),
+           "trsm_batch_autotune")
+    return r
+
+
+def trsm_batch_autotune_lookup(ns, ks, precision: int) -> int:
+    """The recorded block size for a batch like this one, or 0."""
+    if len(ns) != len(ks):
+        raise ValueError("ns and ks must have the same length")
+    an, c = _i64_array(ns)
+    ak, _ = _i64_array(ks)
+    n0 = ctypes.c_int64()
+    _check(_lib.trsm_batch_autotune_lookup(c, an, ak, precision, ctypes.byref(n0)),
+           "trsm_batch_autotune_lookup")
+    return n0.value
 
 
 def trsm_autotune_lookup(n: int, k: int, precision: int):

@@ -116,6 +116,29 @@ def test_mixed_plan_has_low_precision_copies(T):
         T.trsm_plan_destroy(pb)
 
 
+def test_batch_autotune_validation_without_gpu(T):
+    lib = T._lib
+    out = T.BatchTuneResult()
+    n, _ = T._i64_array([100, 200])
+    k, _ = T._i64_array([3, 4])
+    bad0, _ = T._i64_array([100, 0])
+    big, _ = T._i64_array([100, 70000])
+    assert lib.trsm_batch_autotune(0, n, k, T.F64, 2, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, None, k, T.F64, 2, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, n, None, T.F64, 2, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, n, k, T.F64, 0, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, n, k, T.F64, 2, None) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, n, k, T.MIXED_F16, 2, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, bad0, k, T.F64, 2, ctypes.byref(out)) == T.EINVAL
+    assert lib.trsm_batch_autotune(2, big, k, T.F64, 2, ctypes.byref(out)) == T.EINVAL
+    n0 = ctypes.c_int64(-1)
+    assert lib.trsm_batch_autotune_lookup(2, n, k, T.F64, None) == T.EINVAL
+    assert lib.trsm_batch_autotune_lookup(0, n, k, T.F64, ctypes.byref(n0)) == T.EINVAL
+    T.trsm_autotune_clear()
+    assert lib.trsm_batch_autotune_lookup(2, n, k, T.F64, ctypes.byref(n0)) == T.OK
+    assert n0.value == 0
+
+
 def test_plan_tolerance_validation(T):
     lib = T._lib
     assert lib.trsm_plan_set_tolerance(None, 1e-12) == T.EINVAL

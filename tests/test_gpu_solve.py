@@ -451,6 +451,41 @@ def test_batch_matches_oracle_and_is_mix_independent(torch, T, prec, n0, shapes)
         d["s"].close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_autotune_choice_solves_the_batch(torch, T, prec):
+    """trsm_batch_autotune times every candidate block size on synthetic
+    systems of the batch's shapes, records the winner for trsm_batch_
+    autotune_lookup, and a batch made with that block size matches the
+    oracle."""
+    shapes = SHAPES
+    ns, ks = [n for n, _ in shapes], [k for _, k in shapes]
+    T.trsm_autotune_clear()
+    assert T.trsm_batch_autotune_lookup(ns, ks, T.PRECISIONS[prec]) == 0
+    r = T.trsm_batch_autotune(ns, ks, T.PRECISIONS[prec], reps=2)
+    log(f"batch autotune {prec}: n0 {r.n0} ({r.ms:.3f} ms) vs full inversion n0 "
+        f"{r.default_n0} ({r.default_ms:.3f} ms), {r.candidates} candidates")
+    assert r.default_n0 == 2048 and r.candidates == 6       # 2048, then 64 .. 1024
+    assert r.n0 in (64, 128, 256, 512, 1024, 2048)
+    assert 0 < r.ms <= r.default_ms
+    assert T.trsm_batch_autotune_lookup(ns, ks, T.PRECISIONS[prec]) == r.n0
+    sysd, items = _batch_setup(torch, T, shapes, prec, r.n0, 75)
+    b, ws, wsp = _run_batch(torch, T, items, prec, r.n0)
+    T.trsm_batch_check(b, wsp)
+    T.trsm_batch_destroy(b)
+    for d in sysd:
+        X = host(d["Xd"])
+        if prec == "f32":
+            Lr = d["L"].astype(np.float32).astype(np.float64)
+            Br = d["B"].astype(np.float32).astype(np.float64)
+            tol = TOL32
+        else:
+            Lr, Br, tol = d["L"], d["B"], TOL64
+        assert oracle.rel_fro_err(X, oracle.trsm(Lr, Br)) <= tol
+        d["s"].close()
+    T.trsm_autotune_clear()
+    assert T.trsm_batch_autotune_lookup(ns, ks, T.PRECISIONS[prec]) == 0
+
+
 @pytest.mark.parametrize("n0", [128, 64])
 def test_batch_graph_replays_match_eager(torch, T, n0):
     sysd, items = _batch_setup(torch, T, SHAPES[:4], "f64", n0, 90)
