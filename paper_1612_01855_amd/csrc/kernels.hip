@@ -295,35 +295,39 @@ __global__ __launch_bounds__(64) void subst_leaf_kernel(const T* __restrict__ L,
   }
 }
 
-// Deterministic reductions: a fixed grid of kNormBlocks blocks, each thread
-// visiting a fixed set of elements in order, then a fixed-shape tree.
+// Deterministic reductions: a fixed grid of kNormBlocks blocks; block b takes
+// rows b, b + kNormBlocks, ... in order and thread t of it the columns t,
+// t + 256, ... of each row (whole rows per block: coalesced, no index
+// division), then a fixed-shape reduction: butterflies inside each wavefront
+// and a fixed sum of the four wavefronts' results.
 __device__ inline void block_reduce2(double& s, double& mx) {
-  __shared__ double ss[256], sm[256];
-  const int t = threadIdx.x;
-  ss[t] = s;
-  sm[t] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      ss[t] = ss[t] + ss[t + w];
-      sm[t] = fmax(sm[t], sm[t + w]);
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
   }
-  s = ss[0];
-  mx = sm[0];
+  __shared__ double ws[4], wm[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    ws[w] = s;
+    wm[w] = mx;
+  }
+  __syncthreads();
+  s = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  mx = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
 }
 
 __global__ __launch_bounds__(256) void sumsq_max_part(const double* __restrict__ A, int64_t lda,
                                                       int64_t rows, int64_t cols,
                                                       double* __restrict__ part) {
-  const int64_t total = rows * cols;
   double s = 0.0, mx = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)kNormBlocks * 256) {
-    const double v = A[(i / cols) * lda + (i % cols)];
-    s += v * v;
-    mx = fmax(mx, fabs(v));
+  for (int64_t r = blockIdx.x; r < rows; r += kNormBlocks) {
+    const double* __restrict__ a = A + r * lda;
+    for (int64_t c = threadIdx.x; c < cols; c += 256) {
+      const double v = a[c];
+      s += v * v;
+      mx = fmax(mx, fabs(v));
+    }
   }
   block_reduce2(s, mx);
   if (threadIdx.x == 0) {
@@ -335,13 +339,11 @@ __global__ __launch_bounds__(256) void sumsq_max_part(const double* __restrict__
 template <typename TL>
 __global__ __launch_bounds__(256) void sumsq_lower_part(const TL* __restrict__ L, int64_t ldl,
                                                         int64_t n, double* __restrict__ part) {
-  const int64_t total = n * n;
   double s = 0.0, mx = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)kNormBlocks * 256) {
-    const int64_t r = i / n, c = i % n;
-    if (c <= r) {
-      const double v = static_cast<double>(L[r * ldl + c]);
+  for (int64_t r = blockIdx.x; r < n; r += kNormBlocks) {
+    const TL* __restrict__ l = L + r * ldl;
+    for (int64_t c = threadIdx.x; c <= r; c += 256) {
+      const double v = static_cast<double>(l[c]);
       s += v * v;
       mx = fmax(mx, fabs(v));
     }
