@@ -494,8 +494,8 @@ def run_suite(args, torch, T, gen, dev):
     B64 = torch.from_numpy(gen.rhs(n, k, args.seed)).to(dev)
     ms64, _, X64 = time_solves(T, torch, dev, L64, B64, "f64", 0, 0, 3)
     nx = torch.linalg.norm(X64).item()
-    for prec in ("bf16", "f16", "fp8"):
-        s = T.Solver.create(n, k, prec, 0, 0, device=dev)
+    for tol, prec in [(t_, p_) for t_ in (MIXED_TOL, 0.0) for p_ in ("bf16", "f16", "fp8")]:
+        s = T.Solver.create(n, k, prec, 0, 0, device=dev, tolerance=tol)
         X = torch.empty_like(B64)
         inf = T.Info()
         stream = torch.cuda.current_stream().cuda_stream
@@ -511,11 +511,11 @@ def run_suite(args, torch, T, gen, dev):
             times.append(e0.elapsed_time(e1))
         diff = float(torch.linalg.norm(X - X64).item() / nx)
         ms = sorted(times)[1]
-        emit({"suite": "mixed_hard", "n": n, "k": k, "precision": prec,
+        emit({"suite": "mixed_hard", "n": n, "k": k, "precision": prec, "tolerance": tol,
               "status": T.status_string(st), "corrections": inf.iterations,
               "unrefined_error": inf.unrefined_error, "backward_error": inf.backward_error,
               "rel_diff_vs_f64_solve": diff, "ms": round(ms, 3), "f64_ms": round(ms64, 3)})
-        log(f"suite mixed hard {prec}: {T.status_string(st)}, {inf.iterations} corrections, "
+        log(f"suite mixed hard {prec} tolerance {tol:g}: {T.status_string(st)}, {inf.iterations} corrections, "
             f"{ms:.1f} ms (f64 {ms64:.1f} ms), diff vs f64 {diff:.2e}")
         s.close()
         del X
