@@ -367,6 +367,47 @@ def test_mixed_to_tolerance_hard_matrix(torch, T, prec):
     assert berr <= 1e-12
 
 
+@pytest.mark.parametrize("prec,n,k,n0", [("f64", 1100, 70, 256), ("f32", 700, 33, 128),
+                                         ("f64", 300, 5, 0)])
+def test_first_invert_and_solve_capture_into_a_graph(torch, T, prec, n, k, n0):
+    """A fresh plan's first trsm_invert_diag and trsm_solve allocate nothing
+    and set nothing with memset, so both can be captured into a HIP graph;
+    every replay (with eager work and synchronisations between replays) equals
+    the eager result bitwise, which matches the oracle."""
+    dt = torch.float32 if prec == "f32" else torch.float64
+    L, B = gen.easy_system(n, k, 57, upper=np.nan)
+    Ld, Bd = dev(torch, L, dt), dev(torch, B, dt)
+    eager_s = T.Solver.create(n, k, prec, n0)
+    eager_s.invert(Ld)
+    Xe = eager_s.solve(Ld, Bd)
+    torch.cuda.synchronize()
+    eager = host(Xe).copy()
+    eager_s.close()
+    if prec == "f32":
+        Lr, Br, tol = L.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64), TOL32
+    else:
+        Lr, Br, tol = L, B, TOL64
+    assert oracle.rel_fro_err(eager, oracle.trsm(Lr, Br)) <= tol
+    s = T.Solver.create(n, k, prec, n0)           # never used before the capture
+    X = torch.full_like(Bd, float("nan"))
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            T.trsm_invert_diag(s.plan, Ld.data_ptr(), n, s.linv_ptr, side.cuda_stream)
+            T.trsm_solve(s.plan, Ld.data_ptr(), n, s.linv_ptr, Bd.data_ptr(), k, X.data_ptr(), k,
+                         s.workspace_ptr, side.cuda_stream, None)
+    for rep in range(3):
+        X.fill_(float("nan"))                     # eager work between the replays
+        s.linv.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X), eager), rep
+        assert s.last_error() == (T.OK, -1)
+    s.close()
+
+
 # ---- residual entry point -----------------------------------------------------
 
 def test_residual_entry_point(torch, T):
