@@ -403,8 +403,11 @@ trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, 
   hipEvent_t ev_start = look ? P.events[2 * m] : nullptr;
   hipEvent_t ev_end = look ? P.events[2 * m + 1] : nullptr;
   hipStream_t s2 = P.side;
-  // the two streams' products may run at once: no shared split-K scratch
-  SplitScope no_split(look ? nullptr : g_split.ptr, look ? 0 : g_split.bytes);
+  // the two streams' products may run at once: each stream splits K in its
+  // own half of the split-K scratch
+  char* const sp = (char*)g_split.ptr;
+  const int64_t half = sp ? (g_split.bytes / 2) / 256 * 256 : 0;
+  SplitScope crit_split(sp, look ? half : g_split.bytes);
   if (look) {
     TRSM_HIP(hipEventRecord(ev_start, s));
     TRSM_HIP(hipStreamWaitEvent(s2, ev_start, 0));
@@ -436,6 +439,7 @@ trsm_status sweep_right(trsm_plan_s& P, const T* L, int64_t ldl, const T* Linv, 
     const int64_t t1 = t0 + rows_a;
     if (t1 < n) {
       TRSM_HIP(hipStreamWaitEvent(s2, ev_x[i], 0));
+      SplitScope side_split(sp ? sp + half : nullptr, half);
       TRSM_HIP(gemm_simple<T>(L + t1 * ldl + r0, ldl, X + r0 * ldx, ldx, cin + rows_a * ldci, ldci,
                               R + t1 * k, k, n - t1, k, sz, -1.0, 1.0, 0u, s2));
       TRSM_HIP(hipEventRecord(ev_b[i], s2));
