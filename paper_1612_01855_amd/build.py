@@ -32,11 +32,14 @@ FLAGS = [
 ]
 
 
-# Per-source additions.  The factorization leaves keep a row or column of a
-# 64 x 64 block in registers, which needs their fully unrolled step loops;
-# the four-role LU leaf exceeds the compiler's default size limit for a
-# requested full unroll.
-EXTRA = {"factor.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+# Per-source additions.  The factorization leaves and the triangular
+# inversion leaf keep a row or column of a 64 x 64 block in registers, which
+# needs their fully unrolled step loops; the four-role LU leaf and the
+# inversion leaf exceed the compiler's default size limit for a requested
+# full unroll (no other loop in these files is affected: all of them unroll
+# under the default limit).
+_UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000"]
+EXTRA = {"factor.hip": _UNROLL, "kernels.hip": _UNROLL}
 
 
 def _compile(src: str) -> str:

@@ -10,6 +10,9 @@ namespace trsm {
 
 namespace {
 
+// threads for a workgroup that walks one row of n0 elements
+inline unsigned row_threads(int64_t n0) { return (unsigned)std::min<int64_t>(256, (n0 + 63) / 64 * 64); }
+
 inline unsigned grid_for(int64_t work, int threads, int64_t cap = 1 << 20) {
   int64_t g = (work + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -22,16 +25,17 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 1 << 20) {
 // into its own packed buffer (one n0 x n0 binary64 block per S_i).
 // ---------------------------------------------------------------------------
 template <typename TL>
-__global__ void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl, int64_t n,
-                                    int64_t n0, int64_t m, double* __restrict__ Linv,
-                                    unsigned long long* bad, bool upper) {
-  const int64_t per = n0 * n0;
-  const int64_t total = per * m;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = idx / per, e = idx % per;
-    const int64_t i = e / n0, j = e % n0;
-    const int64_t gr = b * n0 + i, gc = b * n0 + j;
+__global__ __launch_bounds__(256) void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl,
+                                                           int64_t n, int64_t n0,
+                                                           double* __restrict__ Linv,
+                                                           unsigned long long* bad, bool upper) {
+  // one row of one packed block per workgroup (row index b n0 + i is also
+  // the global row of L), threads along its columns
+  const int64_t gr = blockIdx.x;
+  const int64_t b = gr / n0, i = gr - b * n0;
+  double* __restrict__ out = Linv + gr * n0;
+  for (int64_t j = threadIdx.x; j < n0; j += blockDim.x) {
+    const int64_t gc = b * n0 + j;
     double v;
     if (gr < n && gc < n) {
       v = (j <= i) ? static_cast<double>(upper ? L[gc * ldl + gr] : L[gr * ldl + gc]) : 0.0;
@@ -39,50 +43,71 @@ __global__ void extract_diag_kernel(const TL* __restrict__ L, int64_t ldl, int64
     } else {
       v = (i == j) ? 1.0 : 0.0;
     }
-    Linv[idx] = v;
+    out[j] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Alg. RecTriInv base case ("sequential inversion"): the nb x nb leaf is
 // inverted by substitution on the identity.  Thread t owns column t of the
-// inverse: x[t][t] = 1 / l[t][t];  x[i][t] = -(sum_{p<i} l[i][p] x[p][t]) / l[i][i]
-// for i > t (entries above the diagonal of the inverse are zero).  All lanes
-// walk the same (i, p) so that l[i][p] is an LDS broadcast.
+// inverse, kept in registers:
+//   x[i] = (delta(i, t) - sum_{p<i} l[i][p] x[p]) / l[i][i],   i = 0 .. 63,
+// which is zero above the diagonal (i < t) and 1 / l[t][t] on it.  Every lane
+// reads the same l[i][p] (an LDS broadcast); the sum runs in four partial
+// sums.  Rows and columns at or beyond nb hold the identity.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void trtri_leaf_kernel(double* __restrict__ Linv, int64_t n0,
                                                         int64_t nb, int64_t lpb) {
-  __shared__ double Ls[64][65];
-  __shared__ double Xs[64][65];
+  __shared__ __attribute__((aligned(16))) double Ls[64][64];
   const int64_t leaf = blockIdx.x;
   const int64_t b = leaf / lpb, q = leaf % lpb;
   double* P = Linv + b * n0 * n0 + q * nb * (n0 + 1);
   const int t = threadIdx.x;
-  for (int i = 0; i < nb; ++i) {
-    Ls[i][t] = (t < nb && t <= i) ? P[(int64_t)i * n0 + t] : 0.0;
-    Xs[i][t] = 0.0;
+  for (int i = 0; i < 64; ++i) {
+    double v;
+    if (i < nb && t < nb) v = (t <= i) ? P[(int64_t)i * n0 + t] : 0.0;
+    else v = (i == t) ? 1.0 : 0.0;
+    Ls[i][t] = v;
   }
   __syncthreads();
-  if (t < nb) Xs[t][t] = 1.0 / Ls[t][t];
-  for (int i = 1; i < nb; ++i) {
-    if (t < i) {
-      double s = 0.0;
-      for (int p = 0; p < i; ++p) s += Ls[i][p] * Xs[p][t];
-      Xs[i][t] = -s / Ls[i][i];
+  double x[64];
+  const double* L0 = &Ls[0][0];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    // Row i is read in groups of 16 entries, each group only after the
+    // previous one is in use (and row i only after x[i-1] exists): the
+    // column of x already takes 128 registers, and reading the whole
+    // triangle ahead would spill.  The empty asm statements only make an
+    // offset depend on an earlier result.
+    int off = i * 64;
+    if (i > 0) asm volatile("" : "+v"(off) : "v"(x[i - 1]));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (16 * g >= i) break;
+      int goff = off + 16 * g;
+      if (g > 0) asm volatile("" : "+v"(goff) : "v"(s4[3]));
+      const double* Lr = L0 + goff;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int p = 16 * g + e;
+        if (p < i) s4[p & 3] = fma(Lr[e], x[p], s4[p & 3]);
+      }
     }
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    x[i] = ((i == t ? 1.0 : 0.0) - s) / Ls[i][i];
   }
-  __syncthreads();
-  for (int i = 0; i < nb; ++i)
-    if (t < nb && t <= i) P[(int64_t)i * n0 + t] = Xs[i][t];
+#pragma unroll
+  for (int i = 0; i < 64; ++i)
+    if (i < nb && t < nb && t <= i) P[(int64_t)i * n0 + t] = x[i];
 }
 
-__global__ void zero_upper_kernel(double* __restrict__ Linv, int64_t n0, int64_t m) {
-  const int64_t per = n0 * n0, total = per * m;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = idx % per;
-    if (e % n0 > e / n0) Linv[idx] = 0.0;
-  }
+__global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ Linv, int64_t n0) {
+  // one row of one packed block per workgroup: its columns past the diagonal
+  const int64_t row = blockIdx.x;
+  const int64_t i = row % n0;
+  double* __restrict__ out = Linv + row * n0;
+  for (int64_t j = i + 1 + threadIdx.x; j < n0; j += blockDim.x) out[j] = 0.0;
 }
 
 template <typename TI, typename TO>
@@ -375,8 +400,8 @@ template <typename TL>
 hipError_t launch_extract_diag(const TL* L, int64_t ldl, int64_t n, int64_t n0, int64_t m,
                                double* Linv, unsigned long long* bad, hipStream_t s, bool upper) {
   if (m <= 0) return hipSuccess;
-  extract_diag_kernel<TL><<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(L, ldl, n, n0, m, Linv, bad,
-                                                                      upper);
+  extract_diag_kernel<TL><<<(unsigned)(m * n0), row_threads(n0), 0, s>>>(L, ldl, n, n0, Linv, bad,
+                                                                         upper);
   return hipGetLastError();
 }
 template hipError_t launch_extract_diag<double>(const double*, int64_t, int64_t, int64_t, int64_t,
@@ -393,7 +418,7 @@ hipError_t launch_trtri_leaf(double* Linv, int64_t n0, int64_t m, int64_t nb, hi
 
 hipError_t launch_zero_upper(double* Linv, int64_t n0, int64_t m, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  zero_upper_kernel<<<grid_for(n0 * n0 * m, 256), 256, 0, s>>>(Linv, n0, m);
+  zero_upper_kernel<<<(unsigned)(m * n0), row_threads(n0), 0, s>>>(Linv, n0);
   return hipGetLastError();
 }
 
