@@ -66,7 +66,9 @@ typedef enum trsm_precision {
 #define TRSM_FLAG_RECURSIVE   0x2u  /* solve with the recursive baseline (Alg. Rec-TRSM order) */
 #define TRSM_FLAG_LOOKAHEAD   0x4u  /* F64/F32 sweep: update the next block's rows first and the
                                        rest on a second stream, overlapping the next diagonal
-                                       apply (launch timings then overlap) */
+                                       apply (launch timings then overlap); each stream splits K
+                                       in its own half of the workspace's split-K scratch.
+                                       Measured slower than the one-stream sweep on MI355X */
 #define TRSM_FLAG_TRANSPOSE   0x10u /* F64/F32: solve L^T X = B (the transposed problem, upper
                                        triangular, backward sweep) with the same L; with a
                                        forward plan this gives A^{-1} B for A = L L^T */
