@@ -589,9 +589,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the solve is measured on one MI355X; see DESIGN.md for how it would shard).",
-              file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the solve is measured on one MI355X).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
