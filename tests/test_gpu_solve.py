@@ -549,6 +549,44 @@ def test_batch_graph_replays_match_eager(torch, T, n0):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lookahead_solve_captures_into_a_graph(torch, T, prec):
+    """The two-stream lookahead sweep forks its side stream from the caller's
+    stream with events and joins it back, so a solve captured on the caller's
+    stream takes the side stream's work into the graph; every replay (with
+    eager work and synchronisations between them) equals the eager solve
+    bitwise."""
+    n, k, n0 = 1500, 70, 128
+    dt = torch.float32 if prec == "f32" else torch.float64
+    L, B = gen.easy_system(n, k, 83, upper=np.nan)
+    Ld, Bd = dev(torch, L, dt), dev(torch, B, dt)
+    s = T.Solver.create(n, k, prec, n0, T.FLAG_LOOKAHEAD)
+    try:
+        side = torch.cuda.Stream()
+        X = torch.full_like(Bd, float("nan"))
+        with torch.cuda.stream(side):
+            T.trsm_invert_diag(s.plan, Ld.data_ptr(), n, s.linv_ptr, side.cuda_stream)
+            T.trsm_solve(s.plan, Ld.data_ptr(), n, s.linv_ptr, Bd.data_ptr(), k, X.data_ptr(), k,
+                         s.workspace_ptr, side.cuda_stream, None)
+        torch.cuda.synchronize()
+        eager = host(X).copy()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                T.trsm_solve(s.plan, Ld.data_ptr(), n, s.linv_ptr, Bd.data_ptr(), k, X.data_ptr(),
+                             k, s.workspace_ptr, side.cuda_stream, None)
+        for rep in range(3):
+            X.fill_(float("nan"))                 # eager work between the replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(host(X), eager), rep
+    finally:
+        s.close()
+    if prec == "f64":
+        assert oracle.rel_fro_err(eager, oracle.trsm(L, B)) <= TOL64
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_lookahead_sweep_matches(torch, T, prec):
     n, k = 1500, 70
     L, B = gen.easy_system(n, k, 81, upper=np.nan)
