@@ -1,7 +1,7 @@
 // Matrix-core GEMM for 8- and 16-bit operands on gfx950 (bfloat16, half,
-// int8), used where the solve runs in low precision: the trailing updates of
-// the bfloat16/half sweep (the update steps of Alg. It-Inv-TRSM on a
-// low-precision copy of L) and the exact integer products of the residual
+// fp8 e4m3, int8), used where the solve runs in low precision: the trailing
+// updates of the bfloat16/half/fp8 sweep (the update steps of Alg.
+// It-Inv-TRSM on a low-precision copy of L) and the exact integer products of the residual
 // B - L X in the refinement (one product per modulus of a residue number
 // system; int8 operands, int32 accumulation, no rounding anywhere).
 //
@@ -11,7 +11,8 @@
 // of C; each wave owns 128 x 64, i.e. 4 x 2 tiles of the 32 x 32 matrix-core
 // instruction (v_mfma_f32_32x32x16_{f16,bf16}, v_mfma_i32_32x32x32_i8: 16
 // bytes of k per lane, the two 32-lane halves taking two different 16-byte
-// pieces).  K advances in chunks of 128 bytes; both operands of a chunk go
+// pieces; v_mfma_scale_f32_32x32x64_f8f6f4 for fp8: 32 bytes per lane, two
+// pieces each).  K advances in chunks of 128 bytes; both operands of a chunk go
 // from HBM straight into LDS (buffer loads with the LDS modifier, no register
 // staging), two LDS stages of 64 KB, one barrier per chunk.  Every row of a
 // stage holds eight 16-byte pieces; piece d of row r sits at position
@@ -39,6 +40,7 @@ namespace lp {
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef int i16v __attribute__((ext_vector_type(16)));
 
@@ -64,6 +66,22 @@ template <> struct Mma<int8_t> {
     return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
   }
 };
+// fp8 (OCP e4m3) on gfx950's f8f6f4 matrix instruction: 64 bytes of k per
+// instruction, 32 per lane (two 16-byte pieces), operand formats 0 (e4m3)
+// and unit block scales (E8M0 127 = 2^0: the operands carry their own
+// power-of-two row and block scales, applied in the epilogue).
+template <> struct Mma<fp8_t> {
+  typedef i8v Frag;
+  typedef f16v Acc;
+  static constexpr int kBytes = 64;
+  static __device__ __forceinline__ Acc mma(Frag a, Frag b, Acc c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+// bytes of k one matrix instruction consumes (16 per lane for the 16-bit
+// and int8 instructions)
+template <typename T> struct KBytes { static constexpr int v = 32; };
+template <> struct KBytes<fp8_t> { static constexpr int v = Mma<fp8_t>::kBytes; };
 
 enum LpFlags : uint32_t {
   LP_A_LOWER = 1u,    // A lower triangular (zeros stored above the diagonal)
@@ -154,7 +172,8 @@ __device__ __forceinline__ void lp_tile(const LpParams& p, int z, int r0, int c0
   constexpr int A_BYTES = kBM * kChunk;
   constexpr int A_INST = kBM / 8 / (kWGM * kWGN), B_INST = kBN / 8 / (kWGM * kWGN);
   constexpr int LOADS = A_INST + B_INST;
-  constexpr int KSTEPS = kChunk / 32;
+  constexpr int KB = KBytes<T>::v;                 // k bytes per instruction
+  constexpr int KSTEPS = kChunk / KB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / kWGN, wn = wave % kWGN;
   const int li = lane & 31, hh = lane >> 5;
@@ -214,18 +233,24 @@ __device__ __forceinline__ void lp_tile(const LpParams& p, int z, int r0, int c0
     const char* as = smem + (c & 1) * kStageBytes;
     const char* bs = as + A_BYTES;
     Frag fa[2][TM], fb[2][TN];
+    // lane group hh takes the pieces (KB / 32) (2 s + hh) .. + KB / 32 - 1 of
+    // k step s, for A and B alike (so every instruction pairs the same k)
+    auto frag = [&](const char* base, int r, int s) {
+      if constexpr (KB == 32) {
+        return *reinterpret_cast<const Frag*>(base + r * kChunk + (((2 * s + hh) ^ piece_pos(r)) * 16));
+      } else {
+        const int d = 4 * s + 2 * hh;
+        const i4v lo = *reinterpret_cast<const i4v*>(base + r * kChunk + ((d ^ piece_pos(r)) * 16));
+        const i4v hi =
+            *reinterpret_cast<const i4v*>(base + r * kChunk + (((d + 1) ^ piece_pos(r)) * 16));
+        return Frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+    };
     auto rd = [&](int s, int set) {
-      const int d = 2 * s + hh;
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = wm * WTM + i * 32 + li;
-        fa[set][i] = *reinterpret_cast<const Frag*>(as + r * kChunk + ((d ^ piece_pos(r)) * 16));
-      }
+      for (int i = 0; i < TM; ++i) fa[set][i] = frag(as, wm * WTM + i * 32 + li, s);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = wn * WTN + j * 32 + li;
-        fb[set][j] = *reinterpret_cast<const Frag*>(bs + r * kChunk + ((d ^ piece_pos(r)) * 16));
-      }
+      for (int j = 0; j < TN; ++j) fb[set][j] = frag(bs, wn * WTN + j * 32 + li, s);
     };
     rd(0, 0);
     issue(c + 1, (c + 1) & 1);   // past the last chunk: zero-filled, never read
@@ -237,7 +262,7 @@ __device__ __forceinline__ void lp_tile(const LpParams& p, int z, int r0, int c0
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(fb[s & 1][j], fa[s & 1][i], acc[i][j]);
     }
-    sched_chunk<0, KSTEPS, TM * TN, TM + TN>();
+    sched_chunk<0, KSTEPS, TM * TN, (TM + TN) * (KB / 32)>();
     if ((p.flags & LP_SEGMENTS) && (c + 1) % p.seg_chunks == 0 && c + 1 < nchunks) {
       // leaving segment j for j + 1: acc <- acc * f(row, j) / f(row, j + 1)
       const int j = (c + 1) / p.seg_chunks - 1;

@@ -523,15 +523,14 @@ trsm_status rec_solve(int64_t n, int64_t k, const T* L, int64_t ldl, T* X, int64
 // written once per block instead of once per step.
 template <typename TL>
 bool low_sweep_left_ok(const trsm_plan_s& P, const TL* Llow, const TL* XlowT) {
-  if constexpr (std::is_same<TL, fp8_t>::value) {
-    return false;
-  } else {
-    lp::LpParams q = lp::lp_params();
-    q.A = Llow; q.lda = P.n;
-    q.B = XlowT; q.ldb = P.n;
-    q.K = (int)P.n0;
-    return P.n % 8 == 0 && P.n0 >= 64 && P.n0 % 64 == 0 && lp::lp_ok<TL>(q);
-  }
+  lp::LpParams q = lp::lp_params();
+  q.A = Llow; q.lda = P.n;
+  q.B = XlowT; q.ldb = P.n;
+  q.K = (int)P.n0;
+  // whole 128-byte chunks per block of K (the segments' scales change at
+  // chunk boundaries)
+  const int64_t bb = P.n0 * (int64_t)sizeof(TL);
+  return P.n % 8 == 0 && bb >= lp::kChunk && bb % lp::kChunk == 0 && lp::lp_ok<TL>(q);
 }
 
 template <typename TL>
@@ -603,11 +602,9 @@ trsm_status low_sweep(const trsm_plan_s& P, const float* Linv32, const TL* Llow,
   const int etarget = std::is_same<TL, f16_t>::value ? 14 : std::is_same<TL, fp8_t>::value ? 6 : 0;
   if (rhs) TRSM_HIP(launch_copy2d<double, float>(rhs, ldr, Rl, k, n, k, scale, s));
   TRSM_HIP(launch_fill_u32(amax, 4 * m, 0u, s));
-  if constexpr (!std::is_same<TL, fp8_t>::value) {
-    if (low_sweep_left_ok<TL>(P, Llow, XlowT))
-      return low_sweep_left<TL>(P, Linv32, Llow, rscale, Rl, D, XlowT, amax, xinv, etarget,
-                                Linv16, linv16_rs, s);
-  }
+  if (low_sweep_left_ok<TL>(P, Llow, XlowT))
+    return low_sweep_left<TL>(P, Linv32, Llow, rscale, Rl, D, XlowT, amax, xinv, etarget,
+                              Linv16, linv16_rs, s);
   for (int64_t i = 0; i < m; ++i) {
     const int64_t r0 = i * n0, sz = std::min(n0, n - r0);
     // D(S_i) = Linv32_ii * Rl(S_i)
