@@ -56,9 +56,10 @@ typedef enum trsm_precision {
   TRSM_MIXED_BF16 = 2,     /* binary64 in/out; sweep products in bfloat16 -> binary32,
                               residual in binary64, iterative refinement */
   TRSM_MIXED_F16 = 3,      /* as above with IEEE half (power-of-two row scaling) */
-  TRSM_MIXED_FP8 = 4       /* experiment: as above with 8-bit e4m3 floats (power-of-two
-                              scales per row and block of L and per solved block of X);
-                              needs more corrections than the 16-bit modes */
+  TRSM_MIXED_FP8 = 4       /* experiment: as above with 8-bit e4m3 floats (OCP e4m3 on the
+                              f8f6f4 matrix instruction; power-of-two scales per row and
+                              block of L and per solved block of X); needs more
+                              corrections than the 16-bit modes */
 } trsm_precision;
 
 /* Plan flags. */
