@@ -85,6 +85,139 @@ __device__ __forceinline__ double pow2_inv_scale(Sq v) {
   return ldexp(1.0, -e);
 }
 
+// Row and column of a thread's elements: those at flat (row-major) index i0,
+// i0 + 256, i0 + 512, ... of a rows x cols matrix, stepped without a division
+// per element (one 64-bit division for the first).
+struct RowCol {
+  int64_t r;
+  int c, dr, dc, cols;
+  __device__ __forceinline__ RowCol(int64_t i0, int ncols) : cols(ncols) {
+    r = i0 / ncols;
+    c = (int)(i0 - r * ncols);
+    dr = 256 / ncols;
+    dc = 256 - dr * ncols;
+  }
+  __device__ __forceinline__ void next() {
+    r += dr;
+    c += dc;
+    if (c >= cols) {
+      c -= cols;
+      ++r;
+    }
+  }
+};
+
+// One element of each elementwise op: the source type S, the destination
+// type D, whether the destination is read (a running sum) and the value
+// stored (`old` is the destination's value for the running sums).
+template <int OP> struct EwElem;
+template <> struct EwElem<EW_F64_TO_F32> {
+  typedef double S; typedef float D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double scale, double) {
+    return static_cast<float>(scale * x);
+  }
+};
+template <> struct EwElem<EW_F32_TO_F64_SET> {
+  typedef float S; typedef double D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double scale, double) {
+    return scale * static_cast<double>(x);
+  }
+};
+template <> struct EwElem<EW_F32_TO_F64_ADD> {
+  typedef float S; typedef double D; static constexpr bool kAdd = true;
+  static __device__ __forceinline__ D f(S x, D old, double scale, double) {
+    return old + scale * static_cast<double>(x);
+  }
+};
+template <> struct EwElem<EW_F64_COPY> {
+  typedef double S; typedef double D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double scale, double) { return scale * x; }
+};
+template <> struct EwElem<EW_F32_COPY> {
+  typedef float S; typedef float D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double scale, double) {
+    return static_cast<float>(scale) * x;
+  }
+};
+template <> struct EwElem<EW_F64_TO_F32_PS> {
+  typedef double S; typedef float D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double, double sc) {
+    return static_cast<float>(sc * x);
+  }
+};
+template <> struct EwElem<EW_F32_TO_F64_SET_SC> {
+  typedef float S; typedef double D; static constexpr bool kAdd = false;
+  static __device__ __forceinline__ D f(S x, D, double, double sc) {
+    return sc * static_cast<double>(x);
+  }
+};
+template <> struct EwElem<EW_F32_TO_F64_ADD_SC> {
+  typedef float S; typedef double D; static constexpr bool kAdd = true;
+  static __device__ __forceinline__ D f(S x, D old, double, double sc) {
+    return old + sc * static_cast<double>(x);
+  }
+};
+template <> struct EwElem<EW_F64_ADD> {
+  typedef double S; typedef double D; static constexpr bool kAdd = true;
+  static __device__ __forceinline__ D f(S x, D old, double, double) { return old + x; }
+};
+
+// Elements a thread keeps in flight: every load of a group is issued before
+// the group's first store, so a workgroup waits for memory once per group
+// rather than once per element.
+constexpr int kEwGroup = 8;
+
+// The thread's elements i0, i0 + 256, ... below lim of one entry.  Padding
+// columns (>= valid_cols) are not read: plain ops store zero there, running
+// sums leave them alone.  Loads are not predicated: an element that is not
+// read loads element (0, 0) instead (every entry has one valid column) and
+// discards it, so the group's loads form one straight run.
+template <int OP>
+__device__ __forceinline__ void ew_elems(const EwEntry& e, int64_t i0, int64_t lim, double sc) {
+  using EL = EwElem<OP>;
+  using S = typename EL::S;
+  using D = typename EL::D;
+  const S* __restrict__ src = static_cast<const S*>(e.src);
+  D* __restrict__ dst = static_cast<D*>(e.dst);
+  if (i0 >= lim || e.valid_cols <= 0) {
+    // nothing to read: plain ops store zeros, running sums are unchanged
+    if (!EL::kAdd)
+      for (; i0 < lim; i0 += 256) {
+        const int64_t r = i0 / e.cols, c = i0 - r * e.cols;
+        dst[r * e.ldd + c] = D(0);
+      }
+    return;
+  }
+  RowCol rc(i0, e.cols);
+  for (; i0 < lim; i0 += 256 * kEwGroup) {
+    int64_t so[kEwGroup], dof[kEwGroup];
+    bool in[kEwGroup], rd[kEwGroup];
+#pragma unroll
+    for (int j = 0; j < kEwGroup; ++j) {
+      in[j] = i0 + 256 * j < lim;
+      rd[j] = in[j] && rc.c < e.valid_cols;
+      so[j] = rd[j] ? rc.r * e.lds + rc.c : 0;
+      dof[j] = in[j] ? rc.r * e.ldd + rc.c : 0;
+      rc.next();
+    }
+    S x[kEwGroup];
+    D old[kEwGroup];
+#pragma unroll
+    for (int j = 0; j < kEwGroup; ++j) {
+      x[j] = src[so[j]];
+      old[j] = EL::kAdd ? dst[dof[j]] : D(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kEwGroup; ++j) {
+      if (EL::kAdd) {
+        if (rd[j]) dst[dof[j]] = EL::f(x[j], old[j], e.scale, sc);
+      } else if (in[j]) {
+        dst[dof[j]] = rd[j] ? EL::f(x[j], old[j], e.scale, sc) : D(0);
+      }
+    }
+  }
+}
+
 // Grouped elementwise kernel: entry e owns workgroups [start[e], start[e+1]),
 // each workgroup converts kEwChunk consecutive elements (row-major order) of
 // its matrix.
@@ -110,56 +243,27 @@ __global__ __launch_bounds__(256) void grouped_ew_kernel(const EwEntry* __restri
   } else if (e.op == EW_F32_TO_F64_SET_SC || e.op == EW_F32_TO_F64_ADD_SC) {
     sc = 1.0 / *e.sc;   // exact: a power of two
   }
-  for (int64_t i = base + threadIdx.x; i < min(total, base + kEwChunk); i += 256) {
-    const int64_t r = i / e.cols, c = i % e.cols;
-    const bool pad = c >= e.valid_cols;
-    switch (e.op) {
-      case EW_F64_TO_F32:
-        static_cast<float*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0f
-                : static_cast<float>(e.scale * static_cast<const double*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F32_TO_F64_SET:
-        static_cast<double*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0 : e.scale * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F32_TO_F64_ADD:
-        if (!pad)
-          static_cast<double*>(e.dst)[r * e.ldd + c] +=
-              e.scale * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F64_COPY:
-        static_cast<double*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0 : e.scale * static_cast<const double*>(e.src)[r * e.lds + c];
-        break;
-      case EW_F64_TO_F32_PS:
-        static_cast<float*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0f : static_cast<float>(sc * static_cast<const double*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F32_TO_F64_SET_SC:
-        static_cast<double*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0 : sc * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F32_TO_F64_ADD_SC:
-        if (!pad)
-          static_cast<double*>(e.dst)[r * e.ldd + c] +=
-              sc * static_cast<double>(static_cast<const float*>(e.src)[r * e.lds + c]);
-        break;
-      case EW_F64_ADD:
-        if (!pad)
-          static_cast<double*>(e.dst)[r * e.ldd + c] += static_cast<const double*>(e.src)[r * e.lds + c];
-        break;
-      default:
-        static_cast<float*>(e.dst)[r * e.ldd + c] =
-            pad ? 0.0f : static_cast<float>(e.scale) * static_cast<const float*>(e.src)[r * e.lds + c];
-        break;
-    }
+  const int64_t i0 = base + threadIdx.x;
+  const int64_t lim = min(total, base + kEwChunk);
+  switch (e.op) {
+    case EW_F64_TO_F32: ew_elems<EW_F64_TO_F32>(e, i0, lim, sc); break;
+    case EW_F32_TO_F64_SET: ew_elems<EW_F32_TO_F64_SET>(e, i0, lim, sc); break;
+    case EW_F32_TO_F64_ADD: ew_elems<EW_F32_TO_F64_ADD>(e, i0, lim, sc); break;
+    case EW_F64_COPY: ew_elems<EW_F64_COPY>(e, i0, lim, sc); break;
+    case EW_F64_TO_F32_PS: ew_elems<EW_F64_TO_F32_PS>(e, i0, lim, sc); break;
+    case EW_F32_TO_F64_SET_SC: ew_elems<EW_F32_TO_F64_SET_SC>(e, i0, lim, sc); break;
+    case EW_F32_TO_F64_ADD_SC: ew_elems<EW_F32_TO_F64_ADD_SC>(e, i0, lim, sc); break;
+    case EW_F64_ADD: ew_elems<EW_F64_ADD>(e, i0, lim, sc); break;
+    default: ew_elems<EW_F32_COPY>(e, i0, lim, sc); break;
   }
 }
 
 // Grouped reductions (see RedOp): entry e owns workgroups [start[e],
 // start[e+1]), one per chunk; the three partial sums of a chunk are merged
-// per wavefront, then over the four wavefronts in order.
+// per wavefront, then over the four wavefronts in order.  A thread adds its
+// elements base + tid, base + tid + 256, ... in that order; it loads them
+// kEwGroup at a time (elements past the chunk read as zero, which leaves a
+// sum of squares unchanged).
 __global__ __launch_bounds__(256) void grouped_red_kernel(const RedEntry* __restrict__ entries,
                                                           const int* __restrict__ start, int n) {
   const int b = blockIdx.x;
@@ -170,22 +274,72 @@ __global__ __launch_bounds__(256) void grouped_red_kernel(const RedEntry* __rest
   const int64_t base = (int64_t)p * e.chunk;
   const int64_t end = min(total, base + e.chunk);
   Sq s0{0.0, kSqEmpty}, s1{0.0, kSqEmpty}, s2{0.0, kSqEmpty};
-  for (int64_t i = base + threadIdx.x; i < end; i += 256) {
-    const int64_t r = i / e.cols, c = i % e.cols;
-    if (e.op == RD_LOAD) {
-      const double v = (c < e.valid_cols && r < e.valid_rows) ? e.a[r * e.lda + c] : 0.0;
-      e.b[r * e.ldb + c] = v;
-      sq_add(s0, v);
-    } else if (e.op == RD_RES) {
-      sq_add(s0, e.a[r * e.lda + c]);
-    } else {
-      const double x = e.b[r * e.ldb + c];
-      sq_add(s0, e.a[r * e.lda + c]);
-      sq_add(s1, x);
-      if (e.d)
-        sq_add(s2, e.d_f64 ? static_cast<const double*>(e.d)[r * e.ldd + c]
-                           : static_cast<double>(static_cast<const float*>(e.d)[r * e.ldd + c]));
-      if (c < e.valid_cols && r < e.valid_rows) e.xo[r * e.ldxo + c] = x;
+  const double* __restrict__ A = e.a;
+  int64_t i0 = base + threadIdx.x;
+  // Loads are not predicated: an element that is not read loads element
+  // (0, 0) of the same matrix instead and is replaced by zero (the caller's
+  // B of RD_LOAD has that element whenever it has a valid row and column).
+  const bool a_any = e.op != RD_LOAD || (e.valid_cols > 0 && e.valid_rows > 0);
+  if (i0 < end) {
+    RowCol rc(i0, e.cols);
+    for (; i0 < end; i0 += 256 * kEwGroup) {
+      int64_t ao[kEwGroup], bo[kEwGroup], dof[kEwGroup], xof[kEwGroup];
+      bool in[kEwGroup], valid[kEwGroup];
+#pragma unroll
+      for (int j = 0; j < kEwGroup; ++j) {
+        in[j] = i0 + 256 * j < end;
+        valid[j] = in[j] && rc.c < e.valid_cols && rc.r < e.valid_rows;
+        const bool rd = e.op == RD_LOAD ? valid[j] : in[j];
+        ao[j] = rd ? rc.r * e.lda + rc.c : 0;
+        bo[j] = in[j] ? rc.r * e.ldb + rc.c : 0;
+        dof[j] = in[j] ? rc.r * e.ldd + rc.c : 0;
+        xof[j] = rc.r * e.ldxo + rc.c;
+        rc.next();
+      }
+      double a[kEwGroup];
+      if (e.op == RD_LOAD) {
+        if (a_any) {
+#pragma unroll
+          for (int j = 0; j < kEwGroup; ++j) a[j] = A[ao[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kEwGroup; ++j) {
+          a[j] = a_any && valid[j] ? a[j] : 0.0;
+          if (in[j]) e.b[bo[j]] = a[j];
+          sq_add(s0, a[j]);
+        }
+      } else if (e.op == RD_RES) {
+#pragma unroll
+        for (int j = 0; j < kEwGroup; ++j) a[j] = A[ao[j]];
+#pragma unroll
+        for (int j = 0; j < kEwGroup; ++j) sq_add(s0, in[j] ? a[j] : 0.0);
+      } else {
+        const double* __restrict__ X = e.b;
+        double x[kEwGroup], d[kEwGroup];
+#pragma unroll
+        for (int j = 0; j < kEwGroup; ++j) {
+          a[j] = A[ao[j]];
+          x[j] = X[bo[j]];
+          d[j] = 0.0;
+        }
+        if (e.d) {
+          if (e.d_f64) {
+#pragma unroll
+            for (int j = 0; j < kEwGroup; ++j) d[j] = static_cast<const double*>(e.d)[dof[j]];
+          } else {
+#pragma unroll
+            for (int j = 0; j < kEwGroup; ++j)
+              d[j] = static_cast<double>(static_cast<const float*>(e.d)[dof[j]]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kEwGroup; ++j) {
+          sq_add(s0, in[j] ? a[j] : 0.0);
+          sq_add(s1, in[j] ? x[j] : 0.0);
+          sq_add(s2, in[j] ? d[j] : 0.0);
+          if (valid[j]) e.xo[xof[j]] = x[j];
+        }
+      }
     }
   }
   __shared__ double rs[4][3];
@@ -226,7 +380,8 @@ __global__ __launch_bounds__(64) void grouped_fin_kernel(const FinEntry* __restr
 
 // Split-K finish of grouped products: the fixed-order sum of each element's
 // ksplit partial sums, then the product's epilogue.  Entry e owns workgroups
-// [start[e], start[e+1]), kFinChunk elements each.
+// [start[e], start[e+1]), kFinChunk elements each; a thread holds its
+// kFinChunk / 256 elements at once, so each slice's loads go out together.
 constexpr int kFinChunk = 2048;
 template <typename T>
 __global__ __launch_bounds__(256) void grouped_split_finish(
@@ -234,6 +389,7 @@ __global__ __launch_bounds__(256) void grouped_split_finish(
     int n) {
   using Acc = typename Mfma<T>::Acc;
   using Epi = EpiType<T, T, T>;
+  constexpr int U = kFinChunk / 256;
   const int b = blockIdx.x;
   const int lo = owner_of(start, n, b);
   const GemmParams<T, T, T, float>& p = entries[lo];
@@ -245,13 +401,56 @@ __global__ __launch_bounds__(256) void grouped_split_finish(
   const bool use_beta = (p.flags & G_BETA) && p.Cin;
   const bool use_rs = (p.flags & G_ROWSCALE) && p.rscale;
   const Acc* __restrict__ P = static_cast<const Acc*>(p.part);
-  for (int64_t e = base + threadIdx.x; e < min(MN, base + kFinChunk); e += 256) {
-    const int row = (int)(e / p.N), col = (int)(e - (int64_t)row * p.N);
-    if ((p.flags & G_C_LOWER) && col > row) continue;
-    Acc v = P[e];
-    for (int t = 1; t < p.ksplit; ++t) v += P[t * MN + e];
-    const Epi rs = use_rs ? static_cast<Epi>(p.rscale[(int64_t)row * p.ld_rs]) : Epi(1);
-    epi_store(p, p.Cout, p.Cin, row, col, static_cast<Epi>(v), alpha, beta, use_beta, rs);
+  const int64_t e0 = base + threadIdx.x;
+  const int64_t lim = min(MN, base + kFinChunk);
+  if (e0 >= lim) return;
+  RowCol rc(e0, p.N);
+  // Loads are not predicated: an element the finish skips (past the chunk,
+  // or above the diagonal of a lower-triangular C) loads the thread's first
+  // element instead, which lies inside every buffer read here, and drops it.
+  int row[U], col[U];
+  int64_t pe[U];
+  bool ok[U];
+  Acc v[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    row[j] = (int)rc.r;
+    col[j] = rc.c;
+    ok[j] = e0 + 256 * j < lim && !((p.flags & G_C_LOWER) && col[j] > row[j]);
+    pe[j] = ok[j] ? e0 + 256 * j : e0;
+    rc.next();
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j) v[j] = P[pe[j]];
+  for (int t = 1; t < p.ksplit; ++t) {
+    const Acc* __restrict__ Pt = P + t * MN;
+    Acc w[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) w[j] = Pt[pe[j]];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] += w[j];
+  }
+  // the epilogue of every element (the same arithmetic as the products'
+  // unsplit epilogue), with its row scales and C inputs loaded up front
+  Epi rs[U], ci[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    const int rj = ok[j] ? row[j] : row[0];
+    const int cj = ok[j] ? col[j] : col[0];
+    rs[j] = use_rs ? static_cast<Epi>(p.rscale[(int64_t)rj * p.ld_rs]) : Epi(1);
+    ci[j] = use_beta ? static_cast<Epi>(p.Cin[(int64_t)rj * p.ldci + cj]) : Epi(0);
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    if (!ok[j]) continue;
+    Epi y = alpha * (static_cast<Epi>(v[j]) * rs[j]);
+    if (use_beta) y += beta * ci[j];
+    p.Cout[(int64_t)row[j] * p.ldco + col[j]] = static_cast<T>(y);
+    if (p.C2) {
+      const float w = cvt<float>(y * static_cast<Epi>(p.c2scale));
+      if (p.flags & G_C2_T) p.C2[(int64_t)col[j] * p.ldc2 + row[j]] = w;
+      else p.C2[(int64_t)row[j] * p.ldc2 + col[j]] = w;
+    }
   }
 }
 
