@@ -459,3 +459,53 @@ def test_served_factors_at_serving_sizes(torch, T):
             assert err <= 1e-12
     finally:
         T.trsm_server_destroy(srv)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_tiny_factors_and_narrow_right_hand_sides(torch, T, precision):
+    # rows and columns below the padding granule (n = 1, 3, 5; k = 1, 2, 3,
+    # 5): the grouped loads, conversions and norm reductions skip the padded
+    # rows and columns of every internal buffer
+    srv = T.trsm_server_create(1 << 30, 32, 0)
+    try:
+        ns = [1, 3, 5, 67, 130]
+        Ls, lids = [], []
+        for i, n in enumerate(ns):
+            L = gen.easy_lower(n, 700 + i, upper=np.nan)
+            Ld = torch.from_numpy(L).cuda()
+            lids.append(T.trsm_server_register_L(srv, Ld.data_ptr(), n, n, precision))
+            Ls.append(L)
+            del Ld
+        torch.cuda.synchronize()
+        reqs = []
+        for f in range(len(ns)):
+            for j, k in enumerate([1, 2, 3, 5, 257]):
+                B = gen.rhs(ns[f], k, 900 + 10 * f + j)
+                Bd = torch.from_numpy(B).cuda()
+                Xd = torch.full_like(Bd, float("nan"))
+                reqs.append(dict(f=f, k=k, B=B, Bd=Bd, Xd=Xd))
+        torch.cuda.synchronize()
+        tickets = [submit(T, srv, lids[q["f"]], q) for q in reqs]
+        res = wait_all(T, srv, tickets)
+        mix = []
+        for q, t in zip(reqs, tickets):
+            st, status, info = res[t]
+            assert st == T.REQ_DONE and status == T.OK
+            X = q["Xd"].cpu().numpy()
+            n = ns[q["f"]]
+            err = oracle.rel_fro_err(X, oracle.trsm(Ls[q["f"]], q["B"]))
+            print(f"request n={n} k={q['k']}: rel err {err:.2e}, "
+                  f"{info.iterations} corrections", flush=True)
+            assert err <= 1e-12
+            check_info(info, n, precision)
+            mix.append((X.copy(), info_tuple(info)))
+        for q, (X, inf) in list(zip(reqs, mix))[::4]:
+            q["Xd"].fill_(float("nan"))
+            torch.cuda.synchronize()
+            t = submit(T, srv, lids[q["f"]], q)
+            st, status, info = wait_all(T, srv, [t])[t]
+            assert st == T.REQ_DONE and status == T.OK
+            assert np.array_equal(q["Xd"].cpu().numpy(), X)
+            assert info_tuple(info) == inf
+    finally:
+        T.trsm_server_destroy(srv)
