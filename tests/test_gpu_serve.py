@@ -465,22 +465,25 @@ def test_served_factors_at_serving_sizes(torch, T):
 def test_tiny_factors_and_narrow_right_hand_sides(torch, T, precision):
     # rows and columns below the padding granule (n = 1, 3, 5; k = 1, 2, 3,
     # 5): the grouped loads, conversions and norm reductions skip the padded
-    # rows and columns of every internal buffer
+    # rows and columns of every internal buffer; triangular and Cholesky
+    # factors share the batches
     srv = T.trsm_server_create(1 << 30, 32, 0)
     try:
-        ns = [1, 3, 5, 67, 130]
+        spec = [(1, False), (3, True), (5, False), (5, True), (67, True), (130, False)]
         Ls, lids = [], []
-        for i, n in enumerate(ns):
-            L = gen.easy_lower(n, 700 + i, upper=np.nan)
+        for i, (n, chol) in enumerate(spec):
+            L = gen.chol_lower(n, 700 + i, upper=np.nan) if chol else \
+                gen.easy_lower(n, 700 + i, upper=np.nan)
             Ld = torch.from_numpy(L).cuda()
-            lids.append(T.trsm_server_register_L(srv, Ld.data_ptr(), n, n, precision))
+            reg = T.trsm_server_register_chol if chol else T.trsm_server_register_L
+            lids.append(reg(srv, Ld.data_ptr(), n, n, precision))
             Ls.append(L)
             del Ld
         torch.cuda.synchronize()
         reqs = []
-        for f in range(len(ns)):
+        for f in range(len(spec)):
             for j, k in enumerate([1, 2, 3, 5, 257]):
-                B = gen.rhs(ns[f], k, 900 + 10 * f + j)
+                B = gen.rhs(spec[f][0], k, 900 + 10 * f + j)
                 Bd = torch.from_numpy(B).cuda()
                 Xd = torch.full_like(Bd, float("nan"))
                 reqs.append(dict(f=f, k=k, B=B, Bd=Bd, Xd=Xd))
@@ -492,12 +495,17 @@ def test_tiny_factors_and_narrow_right_hand_sides(torch, T, precision):
             st, status, info = res[t]
             assert st == T.REQ_DONE and status == T.OK
             X = q["Xd"].cpu().numpy()
-            n = ns[q["f"]]
-            err = oracle.rel_fro_err(X, oracle.trsm(Ls[q["f"]], q["B"]))
-            print(f"request n={n} k={q['k']}: rel err {err:.2e}, "
-                  f"{info.iterations} corrections", flush=True)
+            n, chol = spec[q["f"]]
+            L = Ls[q["f"]]
+            ref = oracle.trsm_t(L, oracle.trsm(L, q["B"])) if chol else oracle.trsm(L, q["B"])
+            err = oracle.rel_fro_err(X, ref)
+            print(f"{'cholesky' if chol else 'triangular'} n={n} k={q['k']}: "
+                  f"rel err {err:.2e}, {info.iterations} corrections", flush=True)
             assert err <= 1e-12
-            check_info(info, n, precision)
+            if chol:
+                assert info.converged == 1
+            else:
+                check_info(info, n, precision)
             mix.append((X.copy(), info_tuple(info)))
         for q, (X, inf) in list(zip(reqs, mix))[::4]:
             q["Xd"].fill_(float("nan"))
