@@ -407,3 +407,23 @@ def test_pivoted_lu_sizes_and_validation_without_gpu(T):
     assert lib.trsm_row_swaps(0, 5, None, None, 4, 4, None) == T.EINVAL
     assert lib.trsm_row_swaps(3, 2, None, None, 4, 4, None) == T.EINVAL
     assert lib.trsm_row_swaps(0, 0, None, None, 4, 4, None) == T.OK             # nothing to do
+
+
+def test_product_path_is_independent_of_the_oracle():
+    # the package and the library it builds name no part of the checker: no
+    # import of `oracle`, no source that includes or links its files, and
+    # the built library does not depend on the oracle's shared object
+    pkg = os.path.join(ROOT, "paper_1612_01855_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath:
+            continue
+        for f in files:
+            if not f.endswith((".py", ".hip", ".hpp", ".h")):
+                continue
+            text = open(os.path.join(dirpath, f)).read()
+            assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+            assert "liboracle" not in text and "oracle.c" not in text, f
+            assert not re.search(r'#include\s+"[^"]*oracle', text), f
+    lib = os.path.join(pkg, "libtrsm.so")
+    if os.path.exists(lib):
+        assert b"liboracle" not in open(lib, "rb").read()
