@@ -427,3 +427,20 @@ def test_product_path_is_independent_of_the_oracle():
     lib = os.path.join(pkg, "libtrsm.so")
     if os.path.exists(lib):
         assert b"liboracle" not in open(lib, "rb").read()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # a copy of the package without libtrsm.so: importing the binding raises
+    # (there is no fallback that could compute anything on the CPU)
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_1612_01855_amd")
+    dst = tmp_path / "paper_1612_01855_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
+    r = subprocess.run([sys.executable, "-c",
+                        "import sys; sys.path.insert(0, sys.argv[1]); "
+                        "from paper_1612_01855_amd import trsm", str(tmp_path)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "libtrsm.so is missing" in r.stderr
